@@ -1,0 +1,257 @@
+"""Pins of the FP64 oracle against exact algebra the paper fixes.
+
+Every expected value here is written from the paper's definitions directly
+(Appendix A matrix and weights, the pressure tensors of Eq. (pt) and Sec. 3.1,
+Eq. (diff)'s moments, the stencils of Eq. (best)) or from textbook identities,
+never from the oracle's own formulas.
+"""
+import numpy as np
+import pytest
+
+from oracle import (Oracle, OracleError, OracleGeom, OracleParams, collide, feq, geq,
+                    gradients, matrix_M, matrix_Minv, solid_mask)
+
+E = np.array([[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1], [1, 1], [-1, -1], [-1, 1], [1, -1]], float)
+VDW = OracleParams(model="vdw", kappa=0.02, a=9 / 49, b=2 / 21, T=0.56, nu_l=0.1, nu_g=0.1)
+BIN = OracleParams(model="binary", kappa=0.04, A=0.04, B=0.04, Gamma=1.0, nu_l=0.5, nu_g=0.05)
+
+
+def test_M_is_orthogonal_basis_of_appendix_A():
+    M = matrix_M()
+    # row norms of the Appendix A basis
+    assert np.allclose(M @ M.T, np.diag([9, 36, 36, 6, 12, 6, 12, 4, 4]), atol=0)
+    Minv = matrix_Minv()
+    assert np.abs(Minv @ M - np.eye(9)).max() < 1e-14
+    assert np.abs(M @ Minv - np.eye(9)).max() < 1e-14
+    D = np.diag(1.0 / np.array([9, 36, 36, 6, 12, 6, 12, 4, 4]))
+    assert np.abs(Minv - M.T @ D).max() < 1e-15
+
+
+def test_M_rows_match_velocity_set():
+    """Rows 0, 3, 5 are density and the two momentum components for the
+    ordering e5=(1,1), e6=(-1,-1), e7=(-1,1), e8=(1,-1); rows 7, 8 are the
+    traceless stresses e_x^2 - e_y^2 and e_x e_y."""
+    M = matrix_M()
+    assert np.array_equal(M[0], np.ones(9))
+    assert np.array_equal(M[3], E[:, 0])
+    assert np.array_equal(M[5], E[:, 1])
+    assert np.array_equal(M[7], E[:, 0] ** 2 - E[:, 1] ** 2)
+    assert np.array_equal(M[8], E[:, 0] * E[:, 1])
+
+
+def _pressure_tensor(kappa, p0, q, lap, dq):
+    """Eq. (pt) / Sec. 3.1: (p0 - kappa q lap q - kappa/2 |grad q|^2) delta + kappa dq dq."""
+    iso = p0 - kappa * q * lap - 0.5 * kappa * (dq @ dq)
+    return iso * np.eye(2) + kappa * np.outer(dq, dq)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_feq_moments_reproduce_pressure_tensor_vdw(seed):
+    rng = np.random.default_rng(seed)
+    rho = rng.uniform(2.6, 4.5)
+    u = rng.uniform(-0.05, 0.05, 2)
+    dq = rng.uniform(-0.3, 0.3, 2)
+    lap = rng.uniform(-0.2, 0.2)
+    omega = rng.uniform(0.6, 1.8)
+    p = VDW
+    p0 = rho * p.T / (1 - p.b * rho) - p.a * rho ** 2
+    X = p0 - p.kappa * rho * lap
+    f = feq(p, rho, u[0], u[1], omega, X, dq[0], dq[1])
+    assert abs(f.sum() - rho) < 1e-13
+    assert np.abs(E.T @ f - rho * u).max() < 1e-14
+    second = np.einsum("i,ia,ib->ab", f, E, E)
+    # Galilean term with lambda = (1/omega - 1/2)(1/3 - dp0/drho)
+    dp0 = p.T / (1 - p.b * rho) ** 2 - 2 * p.a * rho
+    lam = (1 / omega - 0.5) * (1 / 3 - dp0)
+    gal = lam * (np.outer(u, dq) + np.outer(dq, u) + (u @ dq) * np.eye(2))
+    expect = _pressure_tensor(p.kappa, p0, rho, lap, dq) + rho * np.outer(u, u) + gal
+    assert np.abs(second - expect).max() < 1e-13
+    # lambda switched off
+    p1 = OracleParams(**{**p.__dict__, "lambda_mode": 1})
+    f1 = feq(p1, rho, u[0], u[1], omega, X, dq[0], dq[1])
+    second1 = np.einsum("i,ia,ib->ab", f1, E, E)
+    assert np.abs(second1 - (expect - gal)).max() < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_feq_moments_reproduce_pressure_tensor_binary(seed):
+    rng = np.random.default_rng(100 + seed)
+    rho, phi = rng.uniform(0.95, 1.05), rng.uniform(-1.1, 1.1)
+    u = rng.uniform(-0.05, 0.05, 2)
+    dq = rng.uniform(-0.4, 0.4, 2)
+    lap = rng.uniform(-0.2, 0.2)
+    p = BIN
+    p0 = rho / 3 + p.A * (-0.5 * phi ** 2) + p.B * 0.75 * phi ** 4   # Sec. 3.1 bulk pressure
+    X = p0 - p.kappa * phi * lap
+    f = feq(p, rho, u[0], u[1], 1.0, X, dq[0], dq[1])
+    assert abs(f.sum() - rho) < 1e-13
+    assert np.abs(E.T @ f - rho * u).max() < 1e-14
+    second = np.einsum("i,ia,ib->ab", f, E, E)
+    expect = _pressure_tensor(p.kappa, p0, phi, lap, dq) + rho * np.outer(u, u)
+    assert np.abs(second - expect).max() < 1e-13
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_geq_moments_give_advection_diffusion(seed):
+    """Moments behind Eq. (diff): sum g = phi, sum e g = phi u,
+    sum e e g = Gamma mu delta + phi u u."""
+    rng = np.random.default_rng(200 + seed)
+    phi, mu = rng.uniform(-1, 1), rng.uniform(-0.02, 0.02)
+    u = rng.uniform(-0.05, 0.05, 2)
+    g = geq(BIN, phi, u[0], u[1], mu)
+    assert abs(g.sum() - phi) < 1e-15
+    assert np.abs(E.T @ g - phi * u).max() < 1e-15
+    second = np.einsum("i,ia,ib->ab", g, E, E)
+    assert np.abs(second - (BIN.Gamma * mu * np.eye(2) + phi * np.outer(u, u))).max() < 1e-15
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_collision_relaxes_moments_with_rates_S(seed):
+    """m* = m - S (m - m^eq) with S = diag(0,1,1,0,1,0,1,w,w) (Appendix A)."""
+    rng = np.random.default_rng(300 + seed)
+    fe = rng.uniform(0.05, 0.5, 9)
+    f = fe + rng.normal(0, 0.01, 9)
+    M = matrix_M()
+    # equilibrium shares the conserved moments with f
+    dm = M @ (f - fe)
+    dm[[0, 3, 5]] = 0.0
+    f = fe + np.linalg.solve(M, dm)
+    omega = rng.uniform(0.5, 1.9)
+    fs = collide(VDW, f, fe, omega, 0.0, 0.0)
+    m, me, ms = M @ f, M @ fe, M @ fs
+    S = np.array([0, 1, 1, 0, 1, 0, 1, omega, omega])
+    assert np.abs(ms - (m - S * (m - me))).max() < 1e-14
+    # f* does not depend on the non-hydrodynamic moments e, eps, qx, qy of f
+    for k in (1, 2, 4, 6):
+        bump = np.zeros(9)
+        bump[k] = 0.37
+        f2 = f + np.linalg.solve(M, bump)
+        assert np.abs(collide(VDW, f2, fe, omega, 0.0, 0.0) - fs).max() < 1e-14
+
+
+def test_guo_forcing_momentum_and_mass():
+    """Guo et al. (2002): the forcing adds F to the momentum and no mass;
+    with u = (j + F/2)/rho the second moment gains u F + F u (1 - omega/2)
+    on the shear modes."""
+    rng = np.random.default_rng(7)
+    rho = 1.0
+    u = np.array([0.01, -0.004])
+    dq = np.zeros(2)
+    fe = feq(BIN, rho, u[0], u[1], 1.2, rho / 3, 0.0, 0.0)
+    F = np.array([1e-5, 3e-6])
+    j_pre = rho * u - 0.5 * F
+    # a pre-collision f with momentum j_pre and equilibrium elsewhere
+    f = fe.copy()
+    M = matrix_M()
+    dm = np.zeros(9)
+    dm[3], dm[5] = j_pre - rho * u
+    f = f + np.linalg.solve(M, dm)
+    fs = collide(BIN, f, fe, 1.2, u[0], u[1], F[0], F[1])
+    assert abs(fs.sum() - rho) < 1e-15
+    assert np.abs(E.T @ fs - (j_pre + F)).max() < 1e-15
+    _ = rng
+
+
+def test_stencils_exact_on_quadratics():
+    """Eq. (best) stencils are exact for quadratic fields away from walls."""
+    g = OracleGeom(nx=24, ny=20)
+    y, x = np.mgrid[0:20, 0:24].astype(float)
+    q = 0.3 * x * x - 0.7 * x * y + 0.2 * y * y + 1.5 * x - 0.25 * y + 2.0
+    dx, dy, lap = gradients(g, 0.0, q)
+    inner = (slice(2, -2), slice(2, -2))
+    assert np.abs(dx[inner] - (0.6 * x - 0.7 * y + 1.5)[inner]).max() < 1e-11
+    assert np.abs(dy[inner] - (-0.7 * x + 0.4 * y - 0.25)[inner]).max() < 1e-11
+    assert np.abs(lap[inner] - (0.6 + 0.4)).max() < 1e-11
+
+
+@pytest.mark.parametrize("G", [-0.144, 0.0, 0.21])
+def test_wall_gradient_is_imposed_on_flat_walls(G):
+    """Sec. 2.2 wetting: at a node next to a flat wall the normal derivative
+    seen by the equilibrium is exactly the prescribed value (n into fluid)."""
+    g = OracleGeom(nx=16, ny=12, x_in=0, tube_len=16, tube_h=8, y0=2)
+    rng = np.random.default_rng(1)
+    q = rng.uniform(0, 1, (12, 16))
+    dx, dy, lap = gradients(g, G, q)
+    assert np.abs(dy[2, :] - G).max() < 1e-14          # lower wall, n = +y
+    assert np.abs(dy[9, :] + G).max() < 1e-14          # upper wall, n = -y
+    # tangential derivative does not see G
+    dx0, _, _ = gradients(g, 0.0, q)
+    assert np.abs(dx - dx0).max() < 1e-14
+
+
+def test_mask_and_boundary_geometry():
+    g = OracleGeom(nx=10, ny=9, x_in=4, tube_len=5, tube_h=3, y0=3)
+    s = solid_mask(g)
+    assert s.sum() == 5 * (9 - 3)
+    assert not s[:, :4].any() and not s[:, 9].any()
+    assert not s[3:6, 4:9].any() and s[:3, 4:9].all() and s[6:, 4:9].all()
+
+
+def test_init_is_equilibrium_and_rest_stops_boundary_nodes():
+    g = OracleGeom(nx=40, ny=16, x_in=20, tube_len=20, tube_h=6, y0=5)
+    rng = np.random.default_rng(3)
+    q0 = 2.59 + rng.uniform(0, 2, (16, 40))
+    o = Oracle(OracleParams(**{**VDW.__dict__, "wall_grad": -0.1}), g, q0)
+    rho, ux, uy, _ = o.moments()
+    s = solid_mask(g)
+    assert np.abs(rho[~s] - q0[~s]).max() < 1e-13
+    assert np.abs(ux).max() == 0.0 and np.abs(uy).max() == 0.0
+    m0 = rho[~s].sum()
+    o.step(30)
+    rho, ux, uy, _ = o.moments()
+    # boundary nodes: fluid nodes with a solid neighbour
+    bnd = np.zeros_like(s)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            bnd |= np.roll(np.roll(s, -dy, 0), -dx, 1)
+    bnd &= ~s
+    assert bnd.sum() > 0
+    assert np.abs(ux[bnd]).max() < 1e-13 and np.abs(uy[bnd]).max() < 1e-13
+    assert abs(rho[~s].sum() - m0) / m0 < 1e-13
+    assert np.abs(ux[~bnd & ~s]).max() > 1e-6
+
+
+def test_interface_length_definition():
+    """Filled length: linear interpolation of the first centreline crossing."""
+    g = OracleGeom(nx=30, ny=12, x_in=10, tube_len=20, tube_h=4, y0=4)
+    q = np.full((12, 30), 1.0)
+    x = np.arange(30)
+    prof = np.where(x < 10, 1.0, 1.0 - 0.25 * (x - 10))   # crosses 0 at x = 14
+    q[:, :] = prof[None, :]
+    o = Oracle(OracleParams(**{**BIN.__dict__}), g, q)
+    l, le = o.interface_length(0.0)
+    # q_c(k) = 1 - 0.25 k, first k with q_c < 0 is 5: l = 4 + 0/(0 - (-0.25)) = 4
+    assert abs(l - 4.0) < 1e-12 and abs(le - 6.0) < 1e-12
+    l2, _ = o.interface_length(0.1)       # crossing of 0.1 at k = 3.6
+    assert abs(l2 - 3.6) < 1e-12
+    l3, _ = o.interface_length(-10.0)     # never crosses: full tube
+    assert l3 == 20.0
+    l4, _ = o.interface_length(5.0)       # inlet already below
+    assert l4 == 0.0
+
+
+def test_invalid_inputs_are_rejected():
+    g = OracleGeom(nx=20, ny=10)
+    with pytest.raises(OracleError) as e:
+        Oracle(VDW, g, np.full((10, 20), 11.0))     # b rho >= 1
+    assert e.value.code == -1
+    with pytest.raises(OracleError):
+        Oracle(OracleParams(**{**VDW.__dict__, "nu_l": 0.0}), g, np.full((10, 20), 3.0))
+    q = np.full((10, 20), 3.0)
+    q[3, 3] = np.nan
+    with pytest.raises(OracleError):
+        Oracle(VDW, g, q)
+    with pytest.raises(OracleError):
+        Oracle(VDW, OracleGeom(nx=20, ny=10, x_in=5, tube_len=10, tube_h=2, y0=3), np.full((10, 20), 3.0))
+
+
+def test_unstable_run_is_reported():
+    """A density beyond the van der Waals pole during the run is a failure,
+    reported as ORC_EUNSTABLE (-4)."""
+    g = OracleGeom(nx=16, ny=8)
+    q = np.full((8, 16), 3.0)
+    q[:, :8] = 10.4        # just below 1/b = 10.5: the pressure jump blows up
+    o = Oracle(OracleParams(**{**VDW.__dict__, "nu_l": 0.01}), g, q)
+    with pytest.raises(OracleError) as e:
+        o.step(200)
+    assert e.value.code == -4

@@ -1,0 +1,219 @@
+"""Pins of the FP64 oracle against the physics the paper states or implies.
+
+ - coexisting densities of the van der Waals model (Sec. 2: 4.54 / 2.59 printed;
+   the Maxwell construction of the same p0 gives 4.513 / 2.543), binary bulk +-1;
+ - the Laplace law (Sec. 1) with the surface tension of the same model;
+ - Young's law / the Cahn construction for the wetting gradient (Sec. 2.2,
+   Fig. 2): dn rho = -0.144 gives 60 degrees (Sec. 2.2);
+ - Poiseuille flow between no-slip walls, Eq. (1);
+ - Washburn's law, Eq. (3): l_eff^2 linear in t for the binary model at a large
+   viscosity ratio, l linear in t at equal viscosities (Sec. 3.2), and faster
+   than t^1/2 for the liquid-gas model (Sec. 2.2);
+ - conservation of mass and of the order parameter.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, OracleGeom, OracleParams, solid_mask
+from oracle import physics as P
+
+pytestmark = pytest.mark.slow
+
+VDW = dict(model="vdw", kappa=0.02, a=9 / 49, b=2 / 21, T=0.56)
+BIN = dict(model="binary", kappa=0.04, A=0.04, B=0.04, Gamma=1.0)
+
+
+def test_continuum_references():
+    rl, rg = P.vdw_maxwell()
+    assert abs(rl - 4.54) / 4.54 < 0.01 and abs(rg - 2.59) / 2.59 < 0.02     # printed, Sec. 2
+    assert abs(P.vdw_tension() - 0.0112) / 0.0112 < 0.01                      # printed, Sec. 2
+    assert abs(P.vdw_contact_angle(-0.144) - 60.0) < 0.6                      # printed, Sec. 2.2
+    assert abs(P.binary_tension() - 2 * math.sqrt(2) / 3 * 0.04) < 1e-10      # phi^4 closed form
+    assert P.binary_contact_angle(0.0) == 90.0
+
+
+@pytest.mark.parametrize("model", ["vdw", "binary"])
+def test_flat_interface_coexistence(model):
+    nx, ny = 128, 3
+    x = np.arange(nx)
+    slab = (x >= 32) & (x < 96)
+    if model == "vdw":
+        p = OracleParams(**VDW, nu_l=1 / 6, nu_g=1 / 6)
+        q = np.where(slab, 4.5, 2.55)
+    else:
+        p = OracleParams(**BIN, nu_l=1 / 6, nu_g=1 / 6)
+        q = np.where(slab, 1.0, -1.0)
+    o = Oracle(p, OracleGeom(nx, ny), np.repeat(q[None, :].astype(float), ny, 0))
+    o.step(20000)
+    rho, ux, uy, phi = o.moments()
+    fld = rho[1] if model == "vdw" else phi[1]
+    if model == "vdw":
+        rl, rg = P.vdw_maxwell()
+        assert abs(fld.max() - rl) < 1e-3 and abs(fld.min() - rg) < 1e-3
+        assert abs(fld.max() - 4.54) / 4.54 < 0.02 and abs(fld.min() - 2.59) / 2.59 < 0.02
+        gamma_cont = P.vdw_tension()
+    else:
+        assert abs(fld.max() - 1.0) < 1e-3 and abs(fld.min() + 1.0) < 1e-3
+        gamma_cont = P.binary_tension()
+    # excess free energy of the lattice profile: sum kappa (d q/dx)^2 over both interfaces
+    d = (np.roll(fld, -1) - np.roll(fld, 1)) / 2.0
+    gamma_lat = p.kappa * (d * d).sum() / 2.0
+    tol = 0.05 if model == "vdw" else 0.10
+    assert abs(gamma_lat - gamma_cont) / gamma_cont < tol
+    assert np.abs(ux).max() < 1e-6
+
+
+@pytest.mark.parametrize("model", ["vdw", "binary"])
+def test_laplace_law(model):
+    n, R = 64, 18
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    inside = np.hypot(x - n / 2, y - n / 2) < R
+    if model == "vdw":
+        p = OracleParams(**VDW, nu_l=1 / 6, nu_g=1 / 6)
+        q = np.where(inside, 4.5, 2.55)
+    else:
+        p = OracleParams(**BIN, nu_l=1 / 6, nu_g=1 / 6)
+        q = np.where(inside, 1.0, -1.0)
+    o = Oracle(p, OracleGeom(n, n), q)
+    o.step(6000)
+    rho, ux, uy, phi = o.moments()
+    c = n // 2
+    if model == "vdw":
+        rl, rg = P.vdw_maxwell()
+        dp = P.vdw_p0(rho[c, c], p.a, p.b, p.T) - P.vdw_p0(rho[0, 0], p.a, p.b, p.T)
+        area = (rho > 0.5 * (rl + rg)).sum()
+        gamma_ref = P.vdw_tension()
+        tol = 0.05
+    else:
+        p0 = lambda r, f: r / 3 - 0.5 * p.A * f * f + 0.75 * p.B * f ** 4
+        dp = p0(rho[c, c], phi[c, c]) - p0(rho[0, 0], phi[0, 0])
+        area = (phi > 0).sum()
+        gamma_ref = P.binary_tension()
+        tol = 0.10
+    Rm = math.sqrt(area / math.pi)
+    assert dp > 0
+    assert abs(dp * Rm - gamma_ref) / gamma_ref < tol
+
+
+@pytest.mark.parametrize("model,G", [("vdw", -0.144), ("binary", "60"), ("binary", 0.0)])
+def test_young_contact_angle(model, G):
+    """A drop on a flat wall relaxes to the angle set by the wall gradient.
+    The angle is measured against the boundary row, where the rest condition
+    holds the fluid still."""
+    nx, ny = 120, 42
+    g = OracleGeom(nx=nx, ny=ny, x_in=0, tube_len=nx, tube_h=ny - 2, y0=1)
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    inside = np.hypot(x - nx / 2, y - 1) < 22
+    if model == "vdw":
+        p = OracleParams(**VDW, nu_l=1 / 6, nu_g=1 / 6, wall_grad=G)
+        rl, rg = P.vdw_maxwell()
+        q, level, expect, tol = np.where(inside, 4.5, 2.55), 0.5 * (rl + rg), 60.0, 1.5
+    else:
+        Gv = P.binary_wall_gradient(60.0) if G == "60" else G
+        p = OracleParams(**BIN, nu_l=1 / 6, nu_g=1 / 6, wall_grad=Gv)
+        q, level = np.where(inside, 1.0, -1.0), 0.0
+        expect = P.binary_contact_angle(Gv)
+        tol = 2.5 if Gv != 0.0 else 1.0
+    o = Oracle(p, g, q)
+    o.step(15000)
+    rho, ux, uy, phi = o.moments()
+    fld = rho if model == "vdw" else phi
+    theta, _ = P.drop_contact_angle(fld, level, 1.0, mask=solid_mask(g), y_min_fit=4)
+    assert abs(theta - expect) < tol, (theta, expect)
+
+
+@pytest.mark.parametrize("nu", [0.1, 1 / 6, 0.83])
+def test_poiseuille_eq1(nu):
+    """Body-force driven channel flow: exact parabola in the interior, mean
+    velocity F H^2/(12 eta) (Eq. 1 with F = -dp/dx) over the fitted width,
+    and the fitted width within 0.8 of the spacing H-1 of the boundary rows."""
+    H, F = 20, 1e-6
+    g = OracleGeom(nx=3, ny=H + 2, x_in=0, tube_len=3, tube_h=H, y0=1)
+    o = Oracle(OracleParams(**BIN, nu_l=nu, nu_g=nu, force_x=F), g, np.full((H + 2, 3), 1.0))
+    o.step(int(8 * H * H / nu) + 2000)
+    rho, ux, uy, phi = o.moments()
+    u = ux[1:H + 1, 1]
+    y = np.arange(1, H + 1, dtype=float)
+    c = np.polyfit(y[1:-1], u[1:-1], 2)
+    assert np.abs(np.polyval(c, y[1:-1]) - u[1:-1]).max() / u.max() < 1e-4
+    r = np.sort(np.roots(c).real)
+    Hfit = r[1] - r[0]
+    eta = 1.0 * nu
+    # mean of the parabola over its own width equals Eq. (1)
+    xs = np.linspace(r[0], r[1], 20001)
+    mean = np.trapezoid(np.polyval(c, xs), xs) / Hfit
+    assert abs(mean - F * Hfit ** 2 / (12 * eta)) / mean < 1e-3
+    assert abs(Hfit - (H - 1)) < 0.8
+    assert np.abs(uy).max() < 1e-12
+
+
+def _capillary(model, nu_l, nu_g, H=12, L=120, R=80, steps=20000, every=500, l0=10):
+    """Paper geometry (Sec. 2.2): walls are the lattice rows above and below the
+    tube, y-periodic reservoirs, x periodic, liquid column initially l0 into the tube."""
+    ny, nx = H + 2, R + L
+    g = OracleGeom(nx=nx, ny=ny, x_in=R, tube_len=L, tube_h=H, y0=1)
+    x = np.arange(nx)
+    liq = (x >= R // 2) & (x < R + l0)
+    if model == "vdw":
+        rl, rg = P.vdw_maxwell()
+        q = np.where(liq, rl, rg)
+        p = OracleParams(**VDW, nu_l=nu_l, nu_g=nu_l, wall_grad=-0.144)
+        mid = 0.5 * (rl + rg)
+    else:
+        q = np.where(liq, 1.0, -1.0)
+        p = OracleParams(**BIN, nu_l=nu_l, nu_g=nu_g, wall_grad=P.binary_wall_gradient(60.0))
+        mid = 0.0
+    o = Oracle(p, g, np.repeat(q[None, :].astype(float), ny, 0))
+    mass0 = o.moments()[0].sum()
+    phi0 = o.moments()[3].sum()
+    ts, ls = [], []
+    for _ in range(steps // every):
+        o.step(every)
+        ts.append(o.t)
+        ls.append(o.interface_length(mid)[1])
+    rho, _, _, phi = o.moments()
+    return np.array(ts, float), np.array(ls), (mass0, rho.sum()), (phi0, phi.sum())
+
+
+def test_washburn_binary_high_viscosity_ratio():
+    """Sec. 3.2: nu_l = 1.17, nu_g = 0.017 (ratio ~70) follows Eq. (3):
+    l_eff^2 linear in t, with a dynamic angle a little above 60 degrees."""
+    t, le, mass, phis = _capillary("binary", 1.17, 0.017)
+    h = len(t) // 2
+    m, c, r2 = P.linear_fit(t[h:], le[h:] ** 2)
+    assert r2 > 0.999
+    q = len(t) // 4
+    s1 = P.linear_fit(t[q:2 * q], le[q:2 * q] ** 2)[0]
+    s2 = P.linear_fit(t[3 * q:], le[3 * q:] ** 2)[0]
+    assert abs(s2 / s1 - 1) < 0.10
+    # slope of Eq. (3): gamma H cos(theta) / (3 eta) with the lattice tension and
+    # the spacing H-1 of the no-slip boundary rows
+    gamma = 0.035
+    cos_dyn = 3 * 1.17 * m / (gamma * (12 - 1))
+    theta_dyn = math.degrees(math.acos(min(1.0, cos_dyn)))
+    assert 55.0 < theta_dyn < 80.0, theta_dyn
+    assert abs(mass[1] - mass[0]) / mass[0] < 1e-12
+    assert abs(phis[1] - phis[0]) < 1e-9
+
+
+def test_equal_viscosity_fills_linearly():
+    """Sec. 3.2: equal viscosities give l linear in t."""
+    t, le, _, _ = _capillary("binary", 1 / 6, 1 / 6)
+    h = len(t) // 2
+    assert P.linear_fit(t[h:], le[h:])[2] > 0.9999
+    q = len(t) // 4
+    s1 = P.linear_fit(t[q:2 * q], le[q:2 * q] ** 2)[0]
+    s2 = P.linear_fit(t[3 * q:], le[3 * q:] ** 2)[0]
+    assert s2 / s1 - 1 > 0.25      # l^2 is far from linear
+
+
+def test_liquid_gas_fills_faster_than_washburn():
+    """Sec. 2.2: condensation makes l grow faster than t^1/2, so d(l^2)/dt rises."""
+    t, le, mass, _ = _capillary("vdw", 1 / 6, 1 / 6)
+    q = len(t) // 4
+    s1 = P.linear_fit(t[q:2 * q], le[q:2 * q] ** 2)[0]
+    s2 = P.linear_fit(t[3 * q:], le[3 * q:] ** 2)[0]
+    assert s2 / s1 - 1 > 0.08
+    assert abs(mass[1] - mass[0]) / mass[0] < 1e-12
