@@ -1,0 +1,174 @@
+"""Benchmark of the free-energy MRT lattice Boltzmann step on one MI355X.
+
+Default workload: the batched sweep of 256 binary-fluid capillaries of uneven
+size (H ~ U{10..80}, tube length ~ U[500, 4000], reservoir 256 x (H+40),
+viscosity ratio log-uniform in [1, 100], contact angle ~ U[30, 90] degrees,
+master seed 4), all advanced by one kernel launch per time step, replayed from
+HIP graphs, with the filled length of every capillary recorded every 625 steps.
+A step is one time step of all capillaries.  The metric is fluid-node updates
+per second (MLUPS) with the populations resident in HBM before timing starts.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sweep|single4096|single1024]
+
+Prints one JSON line.  Adds the roofline of the step kernel (algorithmic bytes
+per fluid-node update x updates per launch / HIP-event launch time) and the
+FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_LUP = {"vdw": 72, "binary": 144}   # read + write of every stored FP32 population
+
+
+def kernel_source_hash() -> str:
+    path = os.path.join(ROOT, "paper_0911_0459_amd", "csrc", "lb_kernels.h")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if absent or taken on another version of the kernel source."""
+    path = os.path.join(ROOT, "profiles", f"lb_step_kernel_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def build_workload(name: str):
+    from paper_0911_0459_amd import inputs as I
+    if name == "sweep":
+        return I.sweep_batch(4, 256, 100_000), {"workload": "sweep_256_binary_capillaries", "n_capillaries": 256,
+                                              "master_seed": 4, "steps_per_run": 100_000, "sample_every": 625}
+    if name == "single4096":
+        w = I.binary_capillary_4096x256()
+        return [w], {"workload": "binary_4096x256_ratio10_60deg", "lattice": "4096x256", "tube_h": 100,
+                     "tube_len": 3072}
+    if name == "single1024":
+        w = I.binary_capillary_1024x128()
+        return [w], {"workload": "binary_1024x128_ratio10_60deg", "lattice": "1024x128", "tube_h": 40,
+                     "tube_len": 768}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, target_s: float = 15.0):
+    """The FP64 oracle on one capillary of the workload, for a bounded number
+    of steps (calibrated to about target_s seconds)."""
+    import oracle
+    from oracle import Oracle, OracleGeom, OracleParams
+    from oracle import physics as P
+    G = w.wall_grad if w.wall_grad is not None else (
+        P.binary_wall_gradient(w.theta_deg, w.kappa, w.A, w.B) if w.model == "binary"
+        else P.vdw_wall_gradient(w.theta_deg, w.kappa, w.a, w.b, w.T))
+    p = OracleParams(model=w.model, kappa=w.kappa, a=w.a, b=w.b, T=w.T, A=w.A, B=w.B, Gamma=w.Gamma,
+                     nu_l=w.nu_l, nu_g=w.nu_g, wall_grad=G)
+    o = Oracle(p, OracleGeom(**w.geom.asdict()), w.initial_field())
+    fluid = w.geom.fluid_count()
+    t0 = time.perf_counter()
+    o.step(5)
+    dt = time.perf_counter() - t0
+    n = max(5, int(target_s / max(dt / 5, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    return {"value": fluid * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"capillary {w.name} ({w.geom.nx}x{w.geom.ny}, {fluid} fluid nodes), "
+                      f"{n} steps, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "single4096", "single1024"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(capillaries are independent; see DESIGN.md for how the sweep would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_0911_0459_amd import lbcap as L
+
+    torch.cuda.set_device(0)
+    works, config = build_workload(args.workload)
+    model = works[0].model
+    params = [L.params_from_workload(w) for w in works]
+    geoms = [L.geometry_from_workload(w) for w in works]
+    fields = [w.initial_field() for w in works]
+    lat = L.Lattice(params[0], geoms[0], fields[0]) if len(works) == 1 else L.Lattice(params, geoms, fields)
+    del fields
+    if not args.no_autotune:
+        cfg, _ = lat.autotune(trial_steps=10)
+    cfg = lat.launch_config()
+    sample_every = config.get("sample_every", 0)
+
+    lat.step(args.warmup)
+    lat.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(args.steps, sample_every=sample_every)
+    us_kernel = lat.last_step_kernel_us()      # HIP events on the library's stream; synchronises
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lat.check()
+
+    fluid = lat.fluid_nodes
+    mlups = fluid * args.steps / elapsed / 1e6
+    bpl = BYTES_PER_LUP[model]
+    achieved = bpl * fluid / (us_kernel * 1e-6) / 1e9 if us_kernel > 0 else None
+    traffic = traffic_from_profiles(args.workload)
+    config.update({"model": model, "fluid_nodes": fluid, "launch": cfg.asdict(), "bytes_per_lup": bpl})
+    out = {
+        "metric": "MLUPS (fluid-node updates/s) and fraction of HBM roofline",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1000 * elapsed / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": config,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"lb_step_kernel<{1 if model == 'binary' else 0},{cfg.tile_rows},false>",
+            "achieved": round(achieved, 1) if achieved else None,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+            "traffic": traffic,
+            "kernel_us": round(us_kernel, 3),
+        },
+        "cpu_baseline": None,
+    }
+    lat.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(works[0])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

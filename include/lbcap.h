@@ -1,0 +1,261 @@
+/*
+ * lbcap — MI355X library for the D2Q9 free-energy multiple-relaxation-time
+ * lattice Boltzmann scheme of Pooley, Kusumaatmaja & Yeomans, "Modelling
+ * capillary filling dynamics using lattice Boltzmann simulations"
+ * (arXiv:0911.0459): the van der Waals liquid-gas model (Sec. 2) and the
+ * binary model with an order-parameter distribution (Sec. 3), in capillary
+ * geometries (Sec. 2.2, Fig. 1b).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns lb_status; LB_OK is 0, errors are negative.  A
+ *    human-readable message for the last failing call of the calling thread is
+ *    returned by lb_last_error().  No C++ exception crosses this interface.
+ *  - Host arrays are owned by the caller.  Device state is owned by the
+ *    library, unless a device allocation is handed in through d_state (then the
+ *    caller owns that memory and must keep it alive until lb_free).
+ *  - Work is enqueued on the HIP stream given at init (NULL: the library
+ *    creates and owns a stream).  Calls that return host data synchronise that
+ *    stream; lb_step and lb_batch_step only enqueue.
+ *  - Lattice layout of every host field argument: ny*nx doubles, row-major,
+ *    y major (index y*nx + x); x is the tube axis.
+ *  - Units: lattice units, dx = dt = 1 (Sec. 2.1).
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *
+ * Geometry (Sec. 2.2, Fig. 1b).  The lattice is periodic in x.  A tube of
+ * tube_h fluid rows [y0, y0+tube_h) occupies the columns [x_in, x_in+tube_len);
+ * the rows above and below it in those columns are solid walls.  All other
+ * nodes are reservoir, periodic in y.  tube_len = 0 means no walls at all.
+ * Walls are no-slip: bounce-back plus "boundary nodes set to rest" after every
+ * streaming step (Sec. 2.2).  Wetting is set by the normal gradient of rho
+ * (vdW) or phi (binary) seen by the equilibrium at the wall (Sec. 2.2).
+ */
+#ifndef LBCAP_H
+#define LBCAP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,     /* invalid argument: parameters, geometry, buffer size */
+    LB_ENOMEM = -2,     /* device or host allocation failed */
+    LB_EDEVICE = -3,    /* HIP runtime error (no device, launch failure) */
+    LB_EUNSTABLE = -4,  /* non-finite value or non-positive density detected */
+    LB_ESTATE = -5      /* call not valid in the context's current state */
+} lb_status;
+
+typedef enum { LB_VDW = 0, LB_BINARY = 1 } lb_model;
+
+/* Model constants.
+ *  vdW (Sec. 2, Eq. pt): p0 = rho T/(1 - b rho) - a rho^2, gradient coefficient kappa;
+ *    the paper's values are kappa = 0.02, a = 9/49, b = 2/21, T = 0.56.
+ *  binary (Sec. 3.1, Eq. chempot): mu = -A phi + B phi^3 - kappa lap(phi),
+ *    p0 = rho/3 - A phi^2/2 + 3 B phi^4/4; the paper has A = B = kappa = 0.04.
+ *  Gamma: coefficient 2M/dt of mu in g^eq (Appendix A); binary only.
+ *  nu_l, nu_g: kinematic viscosities (Eq. nu; phi clamped to [-1, 1]); the
+ *    relaxation rate is omega = 2/(6 nu + 1) (Appendix A).  vdW uses nu_l.
+ *  wall_grad: normal derivative of rho/phi at the wall, normal into the fluid;
+ *    negative is hydrophilic.  Used when theta_deg is NaN.
+ *  theta_deg: equilibrium contact angle; when not NaN, wall_grad is computed
+ *    with lb_wall_gradient_for_angle.
+ *  force_x: uniform body force along x (Guo, Zheng & Shi 2002 forcing in
+ *    moment space); acts on fluid nodes that are not boundary nodes.
+ *  lambda_mode: 0 uses lambda = (1/omega - 1/2)(1/3 - dp0/drho) in the
+ *    Galilean-correction term of Eq. (equilibrium) for vdW; 1 sets lambda = 0.
+ *    The binary model always uses lambda = 0.
+ *  q_mid: level of rho/phi that marks the interface for the filled length;
+ *    NaN selects 0 (binary) or the mean of the Maxwell coexistence densities
+ *    of p0 (vdW). */
+typedef struct {
+    lb_model model;
+    double kappa, a, b, T;
+    double A, B, Gamma;
+    double nu_l, nu_g;
+    double wall_grad;
+    double theta_deg;
+    double force_x;
+    int lambda_mode;
+    double q_mid;
+} lb_params;
+
+typedef struct {
+    int nx, ny;
+    int x_in, tube_len;
+    int tube_h, y0;
+} lb_geometry;
+
+typedef struct lb_ctx lb_ctx;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lb_last_error(void);
+
+/* Device bytes needed by lb_init for these parameters and this geometry
+ * (two FP32 population buffers, descriptors, tile table, l(t) history).
+ * Returns 0 for invalid arguments. */
+size_t lb_state_bytes(const lb_params* p, const lb_geometry* g);
+
+/* Create a single-lattice context at t = 0 (Sec. 2.2 / 3.2 setups).
+ *  init_q: host, ny*nx doubles: the initial rho (vdW) or phi (binary, rho = 1),
+ *    noise included; values at solid nodes are ignored.  The populations start
+ *    at equilibrium with u = 0 (f = f^eq, g = g^eq, Appendix A).
+ *  d_state/bytes: optional device allocation of at least lb_state_bytes()
+ *    bytes, 256-byte aligned (e.g. from PyTorch); NULL lets the library allocate.
+ *  hip_stream: hipStream_t to enqueue on; NULL creates a library-owned stream.
+ * Validation: 0 < omega < 2 for every viscosity, 0 < b rho < 1 for vdW,
+ * finite values, H >= 3, 1 <= y0, y0 + H <= ny - 1, x_in + tube_len <= nx,
+ * Gamma >= 0.  Errors: LB_EINVAL, LB_ENOMEM, LB_EDEVICE. */
+lb_status lb_init(lb_ctx** out, const lb_params* p, const lb_geometry* g, const double* init_q,
+                  void* d_state, size_t bytes, void* hip_stream);
+
+/* Advance nsteps time steps of Eq. (latbolt) (and Eq. (latbolt2) for the
+ * binary model): moments, stencils of Eq. (best), equilibria, MRT collision
+ * with the rates of Appendix A, streaming with bounce-back, rest of boundary
+ * nodes.  Asynchronous; errors of the launches are reported here, a numerical
+ * blow-up by lb_check or the next call that reads data back. */
+lb_status lb_step(lb_ctx* c, long nsteps);
+
+/* Number of steps taken since lb_init / lb_load. */
+long lb_time(const lb_ctx* c);
+
+/* Scan every fluid node for a non-finite population or rho <= 0; synchronises.
+ * Returns LB_EUNSTABLE (latched for the context) if one is found. */
+lb_status lb_check(lb_ctx* c);
+
+/* Macroscopic fields at the current time into caller-owned host arrays of
+ * ny*nx doubles (any may be NULL): rho, u = (j + F/2)/rho, phi (binary; 0 for
+ * vdW).  Solid nodes get 0.  Synchronises. */
+lb_status lb_moments(lb_ctx* c, double* rho, double* ux, double* uy, double* phi);
+
+/* Same fields as FP32 into caller-owned device arrays of ny*nx floats (any may
+ * be NULL).  Enqueued on the context stream, no synchronisation. */
+lb_status lb_moments_device(lb_ctx* c, float* rho, float* ux, float* uy, float* phi);
+
+/* Filled length l (Fig. 1b) and l_eff = l + H/2 (Sec. 3.2) at the current time:
+ * q on the tube centreline (mean of the two middle rows for even H) is scanned
+ * from x_in; l is the linearly interpolated first position where q drops below
+ * q_mid (0 if the first tube node is already below, tube_len if never).
+ * Synchronises.  LB_EINVAL if the geometry has no tube. */
+lb_status lb_interface_length(lb_ctx* c, double* l, double* l_eff);
+
+/* Wall gradient that gives the equilibrium contact angle theta_deg by Young's
+ * law (Eq. Young) with the surface tensions of the Cahn construction for a
+ * surface energy linear in the wall value of rho/phi (Sec. 2.2, Fig. 2).
+ * Binary model: closed form in the bulk values +-sqrt(A/B).  vdW model:
+ * numerical quadrature of the van der Waals free energy at coexistence.
+ * theta in (0, 180); LB_EINVAL outside the partial-wetting range. */
+lb_status lb_wall_gradient_for_angle(const lb_params* p, double theta_deg, double* grad);
+
+/* Coexisting densities of the van der Waals p0 (equal pressure and chemical
+ * potential, the Maxwell construction) for the constants in p. */
+lb_status lb_vdw_coexistence(const lb_params* p, double* rho_l, double* rho_g);
+
+/* Checkpoint: bytes needed, save into / restore from a caller-owned host
+ * buffer.  The image holds the populations, the step count and a hash of the
+ * parameters and geometry; lb_load refuses an image of another setup
+ * (LB_EINVAL).  Resuming is bitwise identical to not stopping. */
+size_t    lb_checkpoint_bytes(const lb_ctx* c);
+lb_status lb_save(lb_ctx* c, void* host_buf, size_t bytes);
+lb_status lb_load(lb_ctx* c, const void* host_buf, size_t bytes);
+
+/* Release the context (its stream and allocations, not a caller's d_state). */
+void lb_free(lb_ctx* c);
+
+/* ---- batches of capillaries (one launch per step advances all of them) ----
+ * n capillaries, each with its own parameters and geometry (all of the same
+ * model), advance together: every time step is one kernel launch over the
+ * tiles of all lattices, and runs of steps are replayed from HIP graphs.
+ * Capillary k is addressed by its index 0..n-1. */
+lb_status lb_batch_init(lb_ctx** out, int n, const lb_params* p, const lb_geometry* g,
+                        const double* const* init_q, void* hip_stream);
+
+/* Advance every active capillary by nsteps.  If sample_every > 0 the filled
+ * length l_eff of each active capillary is appended to its device history
+ * whenever the step count becomes a multiple of sample_every (capacity
+ * LB_HISTORY_CAP samples; later samples are dropped and reported by
+ * lb_batch_l_history).  Asynchronous. */
+lb_status lb_batch_step(lb_ctx* c, long nsteps, int sample_every);
+
+#define LB_HISTORY_CAP 4096
+
+/* Copy capillary cap's l_eff history into host array l (at most max_samples)
+ * and its length into *n_samples (may exceed max_samples).  Also fills the
+ * step count of each sample into steps if not NULL.  Synchronises. */
+lb_status lb_batch_l_history(lb_ctx* c, int cap, double* l, long* steps, int max_samples,
+                             int* n_samples);
+
+/* Stop advancing capillary cap (accepted by the surrogate gate or failed);
+ * its state is frozen.  lb_batch_revive undoes it. */
+lb_status lb_batch_retire(lb_ctx* c, int cap);
+lb_status lb_batch_revive(lb_ctx* c, int cap);
+
+/* Host fields of one capillary of a batch, as lb_moments.  Synchronises. */
+lb_status lb_batch_moments(lb_ctx* c, int cap, double* rho, double* ux, double* uy, double* phi);
+
+/* Per-capillary health flags after a scan (0 ok, 1 unstable); synchronises.
+ * flags: host array of n ints. */
+lb_status lb_batch_health(lb_ctx* c, int* flags);
+
+/* Number of capillaries and of fluid nodes in the context. */
+int       lb_batch_size(const lb_ctx* c);
+long long lb_fluid_nodes(const lb_ctx* c);
+
+/* Launch configuration of the step kernel.
+ *  tile_rows: rows per tile (1, 2, 4 or 8; tiles are 64 nodes wide).
+ *  schedule: 0 one workgroup per tile in table order, 1 tiles grouped so that
+ *    each of the 8 XCDs of the chip works on a contiguous run of tiles,
+ *    2 persistent workgroups (grid = waves_per_cu x 256 CUs) striding the table.
+ *  graph_steps: steps captured per HIP graph (even, >= 2; 0 = no graphs). */
+typedef struct {
+    int tile_rows;
+    int schedule;
+    int persist_blocks_per_cu;
+    int graph_steps;
+} lb_launch_config;
+
+lb_status lb_get_launch_config(const lb_ctx* c, lb_launch_config* cfg);
+lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg);
+
+/* Autotuner: times the candidate launch configurations on this context's own
+ * lattices (each for `trial_steps` steps, state restored afterwards), keeps
+ * the fastest and returns it with its time per step in microseconds.
+ * The result is cached per (model, tile count class) for later contexts. */
+lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double* us_per_step);
+
+/* Average duration (microseconds) of the step kernel over the launches
+ * enqueued by the last lb_step / lb_batch_step call, measured with HIP events
+ * on the context stream (0 if not available).  Synchronises. */
+lb_status lb_last_step_kernel_us(lb_ctx* c, double* us);
+
+/* ---- learned l(t) surrogate: MLP 19 -> 256 -> 256 -> 256 -> 64, GELU ----
+ * Hand-written HIP kernels for the forward pass, the backward pass and Adam
+ * (Kingma & Ba 2015), FP32, parameters resident on the device.
+ * Inputs and outputs are caller-owned host FP32 arrays, row-major, one row per
+ * sample (n x 19 in, n x 64 out). */
+typedef struct mlp_net mlp_net;
+
+lb_status mlp_init(mlp_net** out, int seed, void* hip_stream);
+void      mlp_free(mlp_net* net);
+/* Number of FP32 parameters (153152 for this architecture). */
+long      mlp_param_count(const mlp_net* net);
+/* Copy parameters (W1,b1,W2,b2,W3,b3,W4,b4; W is out x in row-major) to/from host. */
+lb_status mlp_get_params(mlp_net* net, float* host, long count);
+lb_status mlp_set_params(mlp_net* net, const float* host, long count);
+/* Forward pass for n rows. */
+lb_status mlp_predict(mlp_net* net, const float* X, int n, float* Y);
+/* Mean-squared-error loss and its parameter gradient for n rows (no update);
+ * grads has mlp_param_count floats in the mlp_get_params layout. */
+lb_status mlp_loss_grad(mlp_net* net, const float* X, const float* Y, int n, float* loss,
+                        float* grads);
+/* Train with Adam (beta1 0.9, beta2 0.999, eps 1e-8) on minibatches of
+ * `batch` rows drawn in a seeded shuffled order, for `epochs` passes.
+ * Writes the mean loss of the last epoch into *last_loss if not NULL. */
+lb_status mlp_train(mlp_net* net, const float* X, const float* Y, int n, int epochs, int batch,
+                    float lr, int seed, float* last_loss);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

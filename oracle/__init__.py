@@ -12,6 +12,7 @@ from .oracle import (  # noqa: F401
     Oracle,
     build_oracle,
     lib_path,
+    threads,
     matrix_M,
     matrix_Minv,
     solid_mask,

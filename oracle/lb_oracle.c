@@ -44,6 +44,13 @@ static void set_err(const char* msg) {
 
 const char* orc_error(void) { return g_err; }
 
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif
+
 /* ---- D2Q9 velocity set (Sec. 2.1) ------------------------------------------ */
 static const int EX[9] = {0, 1, -1, 0, 0, 1, -1, -1, 1};
 static const int EY[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};

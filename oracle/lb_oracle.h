@@ -39,6 +39,7 @@ typedef struct {
 typedef struct orc_state orc_state;
 
 const char* orc_error(void);
+int orc_threads(void);   /* OpenMP threads the oracle's loops use */
 
 /* Build the state at t = 0: f = f^eq, g = g^eq of the initial field init_q
  * (ny*nx, row-major, y major): rho for vdW, phi for binary (rho = 1). */

@@ -5,10 +5,9 @@ TEST INFRASTRUCTURE ONLY: see the package docstring.
 from __future__ import annotations
 
 import ctypes as C
-import math
 import os
 import subprocess
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -97,6 +96,7 @@ def _load():
     lib = C.CDLL(_LIB)
     dp = C.POINTER(C.c_double)
     lib.orc_error.restype = C.c_char_p
+    lib.orc_threads.restype = C.c_int
     lib.orc_create.argtypes = [C.POINTER(_Params), C.POINTER(_Geom), dp, C.POINTER(C.c_void_p)]
     lib.orc_create.restype = C.c_int
     lib.orc_free.argtypes = [C.c_void_p]
@@ -128,6 +128,11 @@ def _dp(a: np.ndarray):
 def _check(rc: int):
     if rc != 0:
         raise OracleError(rc, _load().orc_error().decode())
+
+
+def threads() -> int:
+    """OpenMP threads used by the oracle's row loops."""
+    return int(_load().orc_threads())
 
 
 def matrix_M() -> np.ndarray:

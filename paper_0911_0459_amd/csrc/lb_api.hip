@@ -1,0 +1,956 @@
+// Host runtime and C ABI of lbcap (see include/lbcap.h).
+//
+// A context holds one or more capillaries ("a batch") of the same model in a
+// single device allocation:
+//   [CapDev table][tile table][l_now][l history][history steps][history count]
+//   [health flags][population arena A][population arena B]
+// Every capillary owns a region of each arena: 9 FP32 planes of f and, for the
+// binary model, 9 planes of g, each plane ny x pitch with pitch = nx rounded up
+// to 64 floats.  Arena `cur` holds the post-collision populations of the
+// current time; a step pulls from it and writes the other arena.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lbcap.h"
+#include "lb_internal.h"
+#include "lb_kernels.h"
+#include "lb_thermo.h"
+
+using namespace lbk;
+
+namespace {
+
+thread_local std::string g_err;
+
+lb_status fail(lb_status s, const std::string& m) {
+    g_err = m;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(LB_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t v, size_t a = ALIGN) { return (v + a - 1) / a * a; }
+
+bool solid_at(const lb_geometry& g, int x, int y) {
+    x %= g.nx;
+    if (x < 0) x += g.nx;
+    y %= g.ny;
+    if (y < 0) y += g.ny;
+    if (g.tube_len <= 0) return false;
+    if (x < g.x_in || x >= g.x_in + g.tube_len) return false;
+    return y < g.y0 || y >= g.y0 + g.tube_h;
+}
+
+// Every ghost source of the wall rule must be a fluid node.
+bool ghost_sources_fluid(const lb_geometry& g) {
+    if (g.tube_len <= 0) return true;
+    static const int ex[9] = {0, 1, -1, 0, 0, 1, -1, -1, 1};
+    static const int ey[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};
+    auto check_node = [&](int x, int y) -> bool {
+        if (solid_at(g, x, y)) return true;
+        for (int d = 1; d < 9; ++d) {
+            if (!solid_at(g, x + ex[d], y + ey[d])) continue;
+            int sx, sy;
+            if (ex[d] == 0 || ey[d] == 0) {
+                sx = x - ex[d];
+                sy = y - ey[d];
+            } else if (solid_at(g, x + ex[d], y)) {
+                sx = x - ex[d];
+                sy = y + ey[d];
+            } else if (solid_at(g, x, y + ey[d])) {
+                sx = x + ex[d];
+                sy = y - ey[d];
+            } else {
+                sx = x - ex[d];
+                sy = y - ey[d];
+            }
+            if (solid_at(g, sx, sy)) return false;
+        }
+        return true;
+    };
+    // fluid nodes with a solid neighbour lie on the channel's first and last
+    // rows or on the reservoir columns facing the tube's end faces
+    const int rows[2] = {g.y0, g.y0 + g.tube_h - 1};
+    for (int r : rows)
+        for (int x = 0; x < g.nx; ++x)
+            if (!check_node(x, r)) return false;
+    const int cols[2] = {g.x_in - 1, g.x_in + g.tube_len};
+    for (int cx : cols)
+        for (int y = 0; y < g.ny; ++y)
+            if (!check_node(cx, y)) return false;
+    return true;
+}
+
+lb_status validate(const lb_params& p, const lb_geometry& g) {
+    if (p.model != LB_VDW && p.model != LB_BINARY) return fail(LB_EINVAL, "unknown model");
+    if (g.nx < 3 || g.ny < 3) return fail(LB_EINVAL, "lattice must be at least 3x3");
+    if ((long long)g.nx * g.ny > (1LL << 31)) return fail(LB_EINVAL, "lattice too large");
+    if (g.tube_len < 0) return fail(LB_EINVAL, "negative tube length");
+    if (g.tube_len > 0) {
+        if (g.x_in < 0 || g.x_in + g.tube_len > g.nx)
+            return fail(LB_EINVAL, "tube does not fit in the lattice along x");
+        if (g.tube_h < 3 || g.y0 < 1 || g.y0 + g.tube_h > g.ny - 1)
+            return fail(LB_EINVAL, "tube rows must satisfy H >= 3, y0 >= 1, y0 + H <= ny - 1");
+        if (!ghost_sources_fluid(g)) return fail(LB_EINVAL, "wall ghost source is solid (geometry too thin)");
+    }
+    if (!(p.nu_l > 0.0) || !std::isfinite(p.nu_l)) return fail(LB_EINVAL, "nu_l must be positive");
+    if (p.model == LB_BINARY && (!(p.nu_g > 0.0) || !std::isfinite(p.nu_g)))
+        return fail(LB_EINVAL, "nu_g must be positive");
+    if (!(p.kappa >= 0.0) || !std::isfinite(p.kappa)) return fail(LB_EINVAL, "kappa must be >= 0");
+    if (!std::isfinite(p.force_x)) return fail(LB_EINVAL, "force must be finite");
+    if (std::isnan(p.theta_deg) && !std::isfinite(p.wall_grad)) return fail(LB_EINVAL, "wall gradient must be finite");
+    if (!std::isnan(p.theta_deg) && !(p.theta_deg > 0.0 && p.theta_deg < 180.0))
+        return fail(LB_EINVAL, "contact angle must be in (0, 180)");
+    if (p.model == LB_VDW && !(p.b > 0.0 && p.T > 0.0 && std::isfinite(p.a)))
+        return fail(LB_EINVAL, "vdW needs b > 0, T > 0");
+    if (p.model == LB_BINARY && (!(p.Gamma >= 0.0) || !std::isfinite(p.Gamma) || !std::isfinite(p.A) || !std::isfinite(p.B)))
+        return fail(LB_EINVAL, "binary needs finite A, B and Gamma >= 0");
+    return LB_OK;
+}
+
+struct Layout {
+    std::vector<CapDev> caps;
+    long long arena_floats = 0;
+    long long fluid = 0;
+    int max_tiles = 0;
+    size_t off_caps, off_tiles, off_lnow, off_hist, off_hist_t, off_hist_n, off_flags, off_arena0, off_arena1,
+        total;
+};
+
+int count_tiles(const lb_geometry& g, int rows) {
+    int n = 0;
+    for (int y0 = 0; y0 < g.ny; y0 += rows)
+        for (int x0 = 0; x0 < g.nx; x0 += TILE_W) {
+            bool any = false;
+            for (int y = y0; y < std::min(y0 + rows, g.ny) && !any; ++y) {
+                const bool wall_row = g.tube_len > 0 && (y < g.y0 || y >= g.y0 + g.tube_h);
+                if (!wall_row) {
+                    any = true;
+                    break;
+                }
+                const int xe = std::min(x0 + TILE_W, g.nx);
+                if (x0 < g.x_in || xe > g.x_in + g.tube_len) any = true;
+            }
+            n += any;
+        }
+    return n;
+}
+
+void build_tiles(const std::vector<lb_geometry>& G, const std::vector<int>& active, int rows,
+                 std::vector<TileDev>& out) {
+    out.clear();
+    for (size_t k = 0; k < G.size(); ++k) {
+        if (!active[k]) continue;
+        const lb_geometry& g = G[k];
+        for (int y0 = 0; y0 < g.ny; y0 += rows)
+            for (int x0 = 0; x0 < g.nx; x0 += TILE_W) {
+                bool any = false;
+                for (int y = y0; y < std::min(y0 + rows, g.ny) && !any; ++y) {
+                    const bool wall_row = g.tube_len > 0 && (y < g.y0 || y >= g.y0 + g.tube_h);
+                    if (!wall_row) any = true;
+                    const int xe = std::min(x0 + TILE_W, g.nx);
+                    if (x0 < g.x_in || xe > g.x_in + g.tube_len) any = true;
+                }
+                if (any) out.push_back(TileDev{(int)k, x0, y0, std::min(rows, g.ny - y0)});
+            }
+    }
+}
+
+lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L) {
+    L.caps.resize(n);
+    long long off = 0;
+    L.fluid = 0;
+    L.max_tiles = 0;
+    for (int k = 0; k < n; ++k) {
+        const lb_params& p = P[k];
+        const lb_geometry& g = G[k];
+        lb_status s = validate(p, g);
+        if (s) return s;
+        if (p.model != P[0].model) return fail(LB_EINVAL, "all capillaries of a batch must use one model");
+        CapDev c;
+        std::memset(&c, 0, sizeof c);
+        c.nx = g.nx;
+        c.ny = g.ny;
+        c.pitch = (int)align_up((size_t)g.nx, TILE_W);
+        c.x_in = g.tube_len > 0 ? g.x_in : 0;
+        c.x_end = g.tube_len > 0 ? g.x_in + g.tube_len : 0;
+        c.y0 = g.tube_len > 0 ? g.y0 : 0;
+        c.y1 = g.tube_len > 0 ? g.y0 + g.tube_h : 0;
+        c.active = 1;
+        c.plane = (long long)g.ny * c.pitch;
+        c.off_f = off;
+        c.off_g = off + 9 * c.plane;
+        off += (p.model == LB_BINARY ? 18 : 9) * c.plane;
+        c.kappa = (float)p.kappa;
+        c.a = (float)p.a;
+        c.b = (float)p.b;
+        c.T = (float)p.T;
+        c.A = (float)p.A;
+        c.B = (float)p.B;
+        c.Gamma = (float)p.Gamma;
+        c.nu_l = (float)p.nu_l;
+        c.nu_g = (float)(p.model == LB_BINARY ? p.nu_g : p.nu_l);
+        c.omega_l = (float)(2.0 / (6.0 * p.nu_l + 1.0));
+        double G = p.wall_grad;
+        if (!std::isnan(p.theta_deg)) {
+            lb_status s2 = lb_wall_gradient_for_angle(&p, p.theta_deg, &G);
+            if (s2) return s2;
+        }
+        c.G = (float)G;
+        c.Fx = (float)p.force_x;
+        c.lam_on = (p.model == LB_VDW && p.lambda_mode == 0) ? 1.f : 0.f;
+        double qm = p.q_mid;
+        if (std::isnan(qm)) {
+            if (p.model == LB_BINARY) {
+                qm = 0.0;
+            } else {
+                double rl, rg;
+                qm = lbt::vdw_coexistence(p.a, p.b, p.T, &rl, &rg) ? 0.5 * (rl + rg) : 1.0 / (3.0 * p.b);
+            }
+        }
+        c.q_mid = (float)qm;
+        c.hist_off = k * LB_HISTORY_CAP;
+        L.caps[k] = c;
+        long long solid = g.tube_len > 0 ? (long long)g.tube_len * (g.ny - g.tube_h) : 0;
+        L.fluid += (long long)g.nx * g.ny - solid;
+        L.max_tiles += count_tiles(g, 1);
+    }
+    L.arena_floats = off;
+    size_t o = 0;
+    L.off_caps = o;
+    o = align_up(o + sizeof(CapDev) * n);
+    L.off_tiles = o;
+    o = align_up(o + sizeof(TileDev) * (size_t)L.max_tiles);
+    L.off_lnow = o;
+    o = align_up(o + sizeof(float) * n);
+    L.off_hist = o;
+    o = align_up(o + sizeof(float) * (size_t)n * LB_HISTORY_CAP);
+    L.off_hist_t = o;
+    o = align_up(o + sizeof(long long) * (size_t)n * LB_HISTORY_CAP);
+    L.off_hist_n = o;
+    o = align_up(o + sizeof(int) * n);
+    L.off_flags = o;
+    o = align_up(o + sizeof(int) * n);
+    L.off_arena0 = o;
+    o = align_up(o + sizeof(float) * (size_t)L.arena_floats);
+    L.off_arena1 = o;
+    o = align_up(o + sizeof(float) * (size_t)L.arena_floats);
+    L.total = o;
+    return LB_OK;
+}
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ULL) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ULL;
+    }
+    return h;
+}
+
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, lb_launch_config> g_tune_cache;
+
+int size_class(long long fluid) {
+    int c = 0;
+    while (fluid > 1) {
+        fluid >>= 1;
+        ++c;
+    }
+    return c;
+}
+
+}  // namespace
+
+struct lb_ctx {
+    int model = 0;
+    int n = 0;
+    std::vector<lb_params> P;
+    std::vector<lb_geometry> G;
+    Layout L;
+    std::vector<int> active;
+    std::vector<int> frozen_buf;  // arena holding a retired capillary's state
+    char* mem = nullptr;
+    bool own_mem = false;
+    CapDev* d_caps = nullptr;
+    TileDev* d_tiles = nullptr;
+    int ntiles = 0;
+    float* d_lnow = nullptr;
+    float* d_hist = nullptr;
+    long long* d_hist_t = nullptr;
+    int* d_hist_n = nullptr;
+    int* d_flags = nullptr;
+    float* arena[2] = {nullptr, nullptr};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int cur = 0;
+    long t = 0;
+    lb_launch_config cfg{4, 1, 4, 64};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    long timed_steps = 0;
+    int unstable = 0;
+};
+
+namespace {
+
+void drop_graphs(lb_ctx* c) {
+    for (int p = 0; p < 2; ++p) {
+        if (c->gexec[p]) (void)hipGraphExecDestroy(c->gexec[p]);
+        if (c->graph[p]) (void)hipGraphDestroy(c->graph[p]);
+        c->gexec[p] = nullptr;
+        c->graph[p] = nullptr;
+    }
+}
+
+lb_status upload_tiles(lb_ctx* c) {
+    std::vector<TileDev> tiles;
+    build_tiles(c->G, c->active, c->cfg.tile_rows, tiles);
+    if ((int)tiles.size() > c->L.max_tiles) return fail(LB_EINVAL, "tile table overflow");
+    c->ntiles = (int)tiles.size();
+    if (!tiles.empty())
+        HIP_TRY(hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    drop_graphs(c);
+    return LB_OK;
+}
+
+template <int MODEL, int TY, bool INIT>
+void launch_step_t(lb_ctx* c, const StepArgs& a, int grid) {
+    hipLaunchKernelGGL((lb_step_kernel<MODEL, TY, INIT>), dim3(grid), dim3(TILE_W, TY), 0, c->stream, a);
+}
+
+template <int MODEL, bool INIT>
+void launch_step_m(lb_ctx* c, const StepArgs& a, int grid) {
+    switch (c->cfg.tile_rows) {
+        case 1: launch_step_t<MODEL, 1, INIT>(c, a, grid); break;
+        case 2: launch_step_t<MODEL, 2, INIT>(c, a, grid); break;
+        case 8: launch_step_t<MODEL, 8, INIT>(c, a, grid); break;
+        default: launch_step_t<MODEL, 4, INIT>(c, a, grid); break;
+    }
+}
+
+int grid_of(const lb_ctx* c) {
+    const int n = c->ntiles;
+    if (c->cfg.schedule == 1) return 8 * ((n + 7) / 8);
+    if (c->cfg.schedule == 2) return std::max(1, std::min(n, c->cfg.persist_blocks_per_cu * 256));
+    return n;
+}
+
+// Enqueue one step (or the initialisation when init is true) from arena cur.
+void enqueue_step(lb_ctx* c, bool init) {
+    if (c->ntiles == 0) return;
+    StepArgs a;
+    a.caps = c->d_caps;
+    a.tiles = c->d_tiles;
+    a.ntiles = c->ntiles;
+    a.schedule = init ? 0 : c->cfg.schedule;
+    a.src = c->arena[init ? 1 : c->cur];
+    a.dst = c->arena[init ? 0 : c->cur ^ 1];
+    a.init_q = init ? c->arena[1] : nullptr;
+    const int grid = init ? c->ntiles : grid_of(c);
+    if (c->model == LB_VDW) {
+        if (init)
+            launch_step_m<0, true>(c, a, grid);
+        else
+            launch_step_m<0, false>(c, a, grid);
+    } else {
+        if (init)
+            launch_step_m<1, true>(c, a, grid);
+        else
+            launch_step_m<1, false>(c, a, grid);
+    }
+}
+
+lb_status run_steps(lb_ctx* c, long n) {
+    const int K = c->cfg.graph_steps;
+    if (K >= 2 && (K % 2) == 0 && n >= K && c->ntiles > 0) {
+        if (!c->gexec[c->cur]) {
+            const int p = c->cur;
+            HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            for (int s = 0; s < K; ++s) {
+                enqueue_step(c, false);
+                c->cur ^= 1;
+            }
+            hipGraph_t gr = nullptr;
+            HIP_TRY(hipStreamEndCapture(c->stream, &gr));
+            c->graph[p] = gr;
+            HIP_TRY(hipGraphInstantiate(&c->gexec[p], gr, nullptr, nullptr, 0));
+            // capture does not execute: parity is back where it was (K even)
+        }
+        while (n >= K) {
+            HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
+            c->t += K;
+            n -= K;
+        }
+    }
+    for (long s = 0; s < n; ++s) {
+        enqueue_step(c, false);
+        c->cur ^= 1;
+        c->t += 1;
+    }
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status check_ctx(const lb_ctx* c) {
+    if (!c) return fail(LB_EINVAL, "null context");
+    return LB_OK;
+}
+
+lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, const double* const* init_q,
+                 void* d_state, size_t bytes, void* stream) {
+    if (!out) return fail(LB_EINVAL, "null output pointer");
+    *out = nullptr;
+    if (n < 1 || !P || !G || !init_q) return fail(LB_EINVAL, "need at least one capillary with parameters, geometry and initial field");
+    lb_ctx* c = new lb_ctx();
+    c->n = n;
+    c->model = P[0].model;
+    c->P.assign(P, P + n);
+    c->G.assign(G, G + n);
+    lb_status s = make_layout(n, P, G, c->L);
+    if (s) {
+        delete c;
+        return s;
+    }
+    // initial fields: finite, and inside the van der Waals range
+    for (int k = 0; k < n; ++k) {
+        if (!init_q[k]) {
+            delete c;
+            return fail(LB_EINVAL, "null initial field");
+        }
+        const lb_geometry& g = G[k];
+        for (int y = 0; y < g.ny; ++y)
+            for (int x = 0; x < g.nx; ++x) {
+                if (solid_at(g, x, y)) continue;
+                const double v = init_q[k][(size_t)y * g.nx + x];
+                if (!std::isfinite(v)) {
+                    delete c;
+                    return fail(LB_EINVAL, "non-finite initial field");
+                }
+                if (c->model == LB_VDW && !(v > 0.0 && P[k].b * v < 1.0)) {
+                    delete c;
+                    return fail(LB_EINVAL, "vdW initial density must satisfy 0 < rho < 1/b");
+                }
+            }
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        delete c;
+        return fail(LB_EDEVICE, "no HIP device");
+    }
+    if (d_state) {
+        if (bytes < c->L.total || ((uintptr_t)d_state % ALIGN) != 0) {
+            delete c;
+            return fail(LB_EINVAL, "d_state too small or not 256-byte aligned");
+        }
+        c->mem = (char*)d_state;
+    } else {
+        if (hipMalloc(&c->mem, c->L.total) != hipSuccess) {
+            delete c;
+            return fail(LB_ENOMEM, "device allocation of the lattice state failed");
+        }
+        c->own_mem = true;
+    }
+    c->d_caps = (CapDev*)(c->mem + c->L.off_caps);
+    c->d_tiles = (TileDev*)(c->mem + c->L.off_tiles);
+    c->d_lnow = (float*)(c->mem + c->L.off_lnow);
+    c->d_hist = (float*)(c->mem + c->L.off_hist);
+    c->d_hist_t = (long long*)(c->mem + c->L.off_hist_t);
+    c->d_hist_n = (int*)(c->mem + c->L.off_hist_n);
+    c->d_flags = (int*)(c->mem + c->L.off_flags);
+    c->arena[0] = (float*)(c->mem + c->L.off_arena0);
+    c->arena[1] = (float*)(c->mem + c->L.off_arena1);
+    c->active.assign(n, 1);
+    c->frozen_buf.assign(n, 0);
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            lb_free(c);
+            return fail(LB_EDEVICE, "stream creation failed");
+        }
+        c->own_stream = true;
+    }
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+        lb_free(c);
+        return fail(LB_EDEVICE, "event creation failed");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find({c->model, size_class(c->L.fluid)});
+        if (it != g_tune_cache.end()) c->cfg = it->second;
+    }
+    auto bail = [&](lb_status st) {
+        std::string m = g_err;
+        lb_free(c);
+        g_err = m;
+        return st;
+    };
+    if (hipMemcpyAsync(c->d_caps, c->L.caps.data(), sizeof(CapDev) * n, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_hist_n, 0, sizeof(int) * n, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_flags, 0, sizeof(int) * n, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_lnow, 0, sizeof(float) * n, c->stream) != hipSuccess)
+        return bail(fail(LB_EDEVICE, "upload of descriptors failed"));
+    s = upload_tiles(c);
+    if (s) return bail(s);
+    // initial fields go to arena 1 as FP32, at each capillary's f offset
+    for (int k = 0; k < n; ++k) {
+        const lb_geometry& g = G[k];
+        std::vector<float> h((size_t)g.nx * g.ny);
+        for (size_t i = 0; i < h.size(); ++i) h[i] = (float)init_q[k][i];
+        if (hipMemcpyAsync(c->arena[1] + c->L.caps[k].off_f, h.data(), sizeof(float) * h.size(),
+                           hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return bail(fail(LB_EDEVICE, "upload of the initial field failed"));
+    }
+    // the initialisation always uses one workgroup per tile
+    const lb_launch_config keep = c->cfg;
+    enqueue_step(c, true);
+    c->cfg = keep;
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+        return bail(fail(LB_EDEVICE, "initialisation kernel failed"));
+    c->cur = 0;
+    c->t = 0;
+    *out = c;
+    return LB_OK;
+}
+
+// Device region of capillary k in the arena that holds its state.
+float* state_of(lb_ctx* c, int k) { return c->arena[c->active[k] ? c->cur : c->frozen_buf[k]]; }
+
+lb_status moments_into(lb_ctx* c, int k, float* rho, float* ux, float* uy, float* phi) {
+    const float* st = state_of(c, k);
+    const long long n = (long long)c->G[k].nx * c->G[k].ny;
+    const int grid = (int)std::min<long long>((n + 255) / 256, 4096);
+    if (c->model == LB_VDW)
+        hipLaunchKernelGGL(lb_moments_kernel<0>, dim3(grid), dim3(256), 0, c->stream, c->d_caps, k, st, rho, ux,
+                           uy, phi);
+    else
+        hipLaunchKernelGGL(lb_moments_kernel<1>, dim3(grid), dim3(256), 0, c->stream, c->d_caps, k, st, rho, ux,
+                           uy, phi);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status host_moments(lb_ctx* c, int k, double* rho, double* ux, double* uy, double* phi) {
+    const long long n = (long long)c->G[k].nx * c->G[k].ny;
+    // scratch: the same capillary's region of the other arena (its fluid nodes
+    // are rewritten by the next step; a retired capillary's copy is not there)
+    float* scratch = c->arena[(c->active[k] ? c->cur : c->frozen_buf[k]) ^ 1] + c->L.caps[k].off_f;
+    float* out[4] = {scratch, scratch + n, scratch + 2 * n, scratch + 3 * n};
+    lb_status s = moments_into(c, k, out[0], out[1], out[2], out[3]);
+    if (s) return s;
+    std::vector<float> h((size_t)(4 * n));
+    HIP_TRY(hipMemcpyAsync(h.data(), scratch, sizeof(float) * 4 * n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double* dst[4] = {rho, ux, uy, phi};
+    bool bad = false;
+    for (int q = 0; q < 4; ++q) {
+        for (long long i = 0; i < n; ++i) {
+            const float v = h[(size_t)(q * n + i)];
+            if (!std::isfinite(v)) bad = true;
+            if (dst[q]) dst[q][i] = v;
+        }
+    }
+    if (bad) {
+        c->unstable = 1;
+        return fail(LB_EUNSTABLE, "non-finite field");
+    }
+    return LB_OK;
+}
+
+lb_status launch_interface(lb_ctx* c, int record) {
+    hipLaunchKernelGGL(lb_interface_kernel, dim3(c->n), dim3(256), 0, c->stream, c->d_caps, c->n, c->model,
+                       c->arena[c->cur], c->d_lnow, c->d_hist, c->d_hist_t, c->d_hist_n, LB_HISTORY_CAP,
+                       (long long)c->t, record);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status launch_health(lb_ctx* c) {
+    if (c->ntiles == 0) return LB_OK;
+    const int grid = std::min(c->ntiles, 2048);
+    // 512 threads: 8 rows of 64 (tiles have at most 8 rows)
+    if (c->model == LB_VDW)
+        hipLaunchKernelGGL(lb_health_kernel<0>, dim3(grid), dim3(512), 0, c->stream, c->d_caps, c->d_tiles,
+                           c->ntiles, c->arena[c->cur], c->d_flags);
+    else
+        hipLaunchKernelGGL(lb_health_kernel<1>, dim3(grid), dim3(512), 0, c->stream, c->d_caps, c->d_tiles,
+                           c->ntiles, c->arena[c->cur], c->d_flags);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status cap_index(const lb_ctx* c, int cap) {
+    if (cap < 0 || cap >= c->n) return fail(LB_EINVAL, "capillary index out of range");
+    return LB_OK;
+}
+
+// Copy capillary k's region (f, and g) between arenas.
+lb_status copy_region(lb_ctx* c, int k, int from, int to) {
+    const CapDev& d = c->L.caps[k];
+    const long long nf = (c->model == LB_BINARY ? 18 : 9) * d.plane;
+    HIP_TRY(hipMemcpyAsync(c->arena[to] + d.off_f, c->arena[from] + d.off_f, sizeof(float) * nf,
+                           hipMemcpyDeviceToDevice, c->stream));
+    return LB_OK;
+}
+
+lb_status set_active(lb_ctx* c, int k, int on) {
+    if (c->active[k] == on) return LB_OK;
+    if (!on) {
+        c->frozen_buf[k] = c->cur;
+    } else if (c->frozen_buf[k] != c->cur) {
+        lb_status s = copy_region(c, k, c->frozen_buf[k], c->cur);
+        if (s) return s;
+    }
+    c->active[k] = on;
+    c->L.caps[k].active = on;
+    HIP_TRY(hipMemcpyAsync(&c->d_caps[k], &c->L.caps[k], sizeof(CapDev), hipMemcpyHostToDevice, c->stream));
+    return upload_tiles(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+size_t lb_state_bytes(const lb_params* p, const lb_geometry* g) {
+    if (!p || !g) return 0;
+    Layout L;
+    if (make_layout(1, p, g, L) != LB_OK) return 0;
+    return L.total;
+}
+
+lb_status lb_init(lb_ctx** out, const lb_params* p, const lb_geometry* g, const double* init_q, void* d_state,
+                  size_t bytes, void* hip_stream) {
+    const double* q[1] = {init_q};
+    return create(out, 1, p, g, q, d_state, bytes, hip_stream);
+}
+
+lb_status lb_batch_init(lb_ctx** out, int n, const lb_params* p, const lb_geometry* g, const double* const* init_q,
+                        void* hip_stream) {
+    return create(out, n, p, g, init_q, nullptr, 0, hip_stream);
+}
+
+lb_status lb_step(lb_ctx* c, long nsteps) { return lb_batch_step(c, nsteps, 0); }
+
+lb_status lb_batch_step(lb_ctx* c, long nsteps, int sample_every) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (nsteps < 0 || sample_every < 0) return fail(LB_EINVAL, "negative step count");
+    HIP_TRY(hipEventRecord(c->ev0, c->stream));
+    long left = nsteps;
+    while (left > 0) {
+        long chunk = left;
+        if (sample_every > 0) chunk = std::min(left, sample_every - (c->t % sample_every));
+        lb_status s = run_steps(c, chunk);
+        if (s) return s;
+        left -= chunk;
+        if (sample_every > 0 && c->t % sample_every == 0) {
+            if ((s = launch_interface(c, 1))) return s;
+            if ((s = launch_health(c))) return s;
+        }
+    }
+    HIP_TRY(hipEventRecord(c->ev1, c->stream));
+    c->timed_steps = nsteps;
+    return LB_OK;
+}
+
+lb_status lb_last_step_kernel_us(lb_ctx* c, double* us) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (!us) return fail(LB_EINVAL, "null output");
+    *us = 0.0;
+    if (c->timed_steps <= 0) return LB_OK;
+    HIP_TRY(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    *us = 1000.0 * ms / (double)c->timed_steps;
+    return LB_OK;
+}
+
+long lb_time(const lb_ctx* c) { return c ? c->t : -1; }
+
+int lb_batch_size(const lb_ctx* c) { return c ? c->n : 0; }
+
+long long lb_fluid_nodes(const lb_ctx* c) { return c ? c->L.fluid : 0; }
+
+lb_status lb_batch_health(lb_ctx* c, int* flags) {
+    if (lb_status s = check_ctx(c)) return s;
+    HIP_TRY(hipMemsetAsync(c->d_flags, 0, sizeof(int) * c->n, c->stream));
+    if (lb_status s = launch_health(c)) return s;
+    std::vector<int> h(c->n);
+    HIP_TRY(hipMemcpyAsync(h.data(), c->d_flags, sizeof(int) * c->n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    bool any = false;
+    for (int k = 0; k < c->n; ++k) {
+        if (flags) flags[k] = h[k];
+        any |= h[k] != 0;
+    }
+    if (any) {
+        c->unstable = 1;
+        return fail(LB_EUNSTABLE, "non-finite population or non-positive density");
+    }
+    return LB_OK;
+}
+
+lb_status lb_check(lb_ctx* c) {
+    if (lb_status s = check_ctx(c)) return s;
+    lb_status s = lb_batch_health(c, nullptr);
+    if (s == LB_OK && c->unstable) return fail(LB_EUNSTABLE, "instability latched earlier");
+    return s;
+}
+
+lb_status lb_moments(lb_ctx* c, double* rho, double* ux, double* uy, double* phi) {
+    return lb_batch_moments(c, 0, rho, ux, uy, phi);
+}
+
+lb_status lb_batch_moments(lb_ctx* c, int cap, double* rho, double* ux, double* uy, double* phi) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (lb_status s = cap_index(c, cap)) return s;
+    return host_moments(c, cap, rho, ux, uy, phi);
+}
+
+lb_status lb_moments_device(lb_ctx* c, float* rho, float* ux, float* uy, float* phi) {
+    if (lb_status s = check_ctx(c)) return s;
+    return moments_into(c, 0, rho, ux, uy, phi);
+}
+
+lb_status lb_interface_length(lb_ctx* c, double* l, double* l_eff) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (c->G[0].tube_len <= 0) return fail(LB_EINVAL, "no tube in this geometry");
+    if (!c->active[0]) return fail(LB_ESTATE, "capillary is retired");
+    if (lb_status s = launch_interface(c, 0)) return s;
+    float h = 0.f;
+    HIP_TRY(hipMemcpyAsync(&h, c->d_lnow, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (!std::isfinite(h)) return fail(LB_EUNSTABLE, "non-finite interface position");
+    if (l) *l = h;
+    if (l_eff) *l_eff = h + 0.5 * c->G[0].tube_h;
+    return LB_OK;
+}
+
+lb_status lb_batch_l_history(lb_ctx* c, int cap, double* l, long* steps, int max_samples, int* n_samples) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (lb_status s = cap_index(c, cap)) return s;
+    int n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, c->d_hist_n + cap, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const int m = std::min(std::min(n, LB_HISTORY_CAP), std::max(max_samples, 0));
+    if (m > 0) {
+        std::vector<float> h(m);
+        std::vector<long long> ht(m);
+        HIP_TRY(hipMemcpyAsync(h.data(), c->d_hist + c->L.caps[cap].hist_off, sizeof(float) * m,
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipMemcpyAsync(ht.data(), c->d_hist_t + c->L.caps[cap].hist_off, sizeof(long long) * m,
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < m; ++i) {
+            if (l) l[i] = h[i];
+            if (steps) steps[i] = (long)ht[i];
+        }
+    }
+    if (n_samples) *n_samples = n;
+    return LB_OK;
+}
+
+lb_status lb_batch_retire(lb_ctx* c, int cap) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (lb_status s = cap_index(c, cap)) return s;
+    return set_active(c, cap, 0);
+}
+
+lb_status lb_batch_revive(lb_ctx* c, int cap) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (lb_status s = cap_index(c, cap)) return s;
+    return set_active(c, cap, 1);
+}
+
+lb_status lb_wall_gradient_for_angle(const lb_params* p, double theta_deg, double* grad) {
+    if (!p || !grad) return fail(LB_EINVAL, "null argument");
+    bool ok;
+    if (p->model == LB_BINARY)
+        ok = lbt::binary_wall_gradient(p->kappa, p->A, p->B, theta_deg, grad);
+    else
+        ok = lbt::vdw_wall_gradient(p->kappa, p->a, p->b, p->T, theta_deg, grad);
+    if (!ok) return fail(LB_EINVAL, "no partial-wetting wall gradient for this angle and these constants");
+    return LB_OK;
+}
+
+lb_status lb_vdw_coexistence(const lb_params* p, double* rho_l, double* rho_g) {
+    if (!p || !rho_l || !rho_g) return fail(LB_EINVAL, "null argument");
+    if (!lbt::vdw_coexistence(p->a, p->b, p->T, rho_l, rho_g)) return fail(LB_EINVAL, "no coexistence (T >= Tc?)");
+    return LB_OK;
+}
+
+struct CkptHeader {
+    uint64_t magic;
+    uint64_t hash;
+    int64_t t;
+    int32_t n, model;
+    int64_t floats;
+};
+
+static uint64_t setup_hash(const lb_ctx* c) {
+    uint64_t h = fnv1a(c->P.data(), sizeof(lb_params) * c->P.size());
+    return fnv1a(c->G.data(), sizeof(lb_geometry) * c->G.size(), h);
+}
+
+size_t lb_checkpoint_bytes(const lb_ctx* c) {
+    if (!c) return 0;
+    return sizeof(CkptHeader) + sizeof(int) * c->n + sizeof(float) * (size_t)c->L.arena_floats;
+}
+
+lb_status lb_save(lb_ctx* c, void* host_buf, size_t bytes) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (!host_buf || bytes < lb_checkpoint_bytes(c)) return fail(LB_EINVAL, "checkpoint buffer too small");
+    CkptHeader h{0x4C42434150434B31ULL, setup_hash(c), c->t, c->n, c->model, c->L.arena_floats};
+    char* p = (char*)host_buf;
+    std::memcpy(p, &h, sizeof h);
+    std::memcpy(p + sizeof h, c->active.data(), sizeof(int) * c->n);
+    float* dst = (float*)(p + sizeof h + sizeof(int) * c->n);
+    for (int k = 0; k < c->n; ++k) {
+        const CapDev& d = c->L.caps[k];
+        const long long nf = (c->model == LB_BINARY ? 18 : 9) * d.plane;
+        HIP_TRY(hipMemcpyAsync(dst + d.off_f, state_of(c, k) + d.off_f, sizeof(float) * nf, hipMemcpyDeviceToHost,
+                               c->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+lb_status lb_load(lb_ctx* c, const void* host_buf, size_t bytes) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (!host_buf || bytes < lb_checkpoint_bytes(c)) return fail(LB_EINVAL, "checkpoint buffer too small");
+    CkptHeader h;
+    std::memcpy(&h, host_buf, sizeof h);
+    if (h.magic != 0x4C42434150434B31ULL || h.hash != setup_hash(c) || h.n != c->n || h.floats != c->L.arena_floats)
+        return fail(LB_EINVAL, "checkpoint belongs to another setup");
+    const char* p = (const char*)host_buf;
+    std::vector<int> act(c->n);
+    std::memcpy(act.data(), p + sizeof h, sizeof(int) * c->n);
+    const float* src = (const float*)(p + sizeof h + sizeof(int) * c->n);
+    HIP_TRY(hipMemcpyAsync(c->arena[c->cur], src, sizeof(float) * c->L.arena_floats, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < c->n; ++k) {
+        c->active[k] = act[k] ? 1 : 0;
+        c->frozen_buf[k] = c->cur;
+        c->L.caps[k].active = c->active[k];
+    }
+    HIP_TRY(hipMemcpyAsync(c->d_caps, c->L.caps.data(), sizeof(CapDev) * c->n, hipMemcpyHostToDevice, c->stream));
+    c->t = (long)h.t;
+    c->unstable = 0;
+    return upload_tiles(c);
+}
+
+lb_status lb_get_launch_config(const lb_ctx* c, lb_launch_config* cfg) {
+    if (!c || !cfg) return fail(LB_EINVAL, "null argument");
+    *cfg = c->cfg;
+    return LB_OK;
+}
+
+lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
+    if (!c || !cfg) return fail(LB_EINVAL, "null argument");
+    const int r = cfg->tile_rows;
+    if (r != 1 && r != 2 && r != 4 && r != 8) return fail(LB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
+    if (cfg->schedule < 0 || cfg->schedule > 2) return fail(LB_EINVAL, "schedule must be 0, 1 or 2");
+    if (cfg->schedule == 2 && (cfg->persist_blocks_per_cu < 1 || cfg->persist_blocks_per_cu > 32))
+        return fail(LB_EINVAL, "persistent workgroups per CU must be in 1..32");
+    if (cfg->graph_steps != 0 && (cfg->graph_steps < 2 || cfg->graph_steps % 2 != 0 || cfg->graph_steps > 4096))
+        return fail(LB_EINVAL, "graph_steps must be 0 or an even number in 2..4096");
+    const bool retile = r != c->cfg.tile_rows;
+    c->cfg = *cfg;
+    drop_graphs(c);
+    if (retile) return upload_tiles(c);
+    return LB_OK;
+}
+
+lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double* us_per_step) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (trial_steps < 2) return fail(LB_EINVAL, "trial_steps must be >= 2");
+    // back up the current state: the trials advance the lattices
+    float* backup = nullptr;
+    HIP_TRY(hipMalloc(&backup, sizeof(float) * (size_t)c->L.arena_floats));
+    HIP_TRY(hipMemcpyAsync(backup, c->arena[c->cur], sizeof(float) * (size_t)c->L.arena_floats,
+                           hipMemcpyDeviceToDevice, c->stream));
+    const long t0 = c->t;
+    const int cur0 = c->cur;
+    const lb_launch_config orig = c->cfg;
+    std::vector<lb_launch_config> cand;
+    for (int r : {1, 2, 4, 8}) {
+        cand.push_back({r, 0, 4, 0});
+        cand.push_back({r, 1, 4, 0});
+        cand.push_back({r, 2, 4, 0});
+        cand.push_back({r, 2, 8, 0});
+    }
+    double best_us = 1e300;
+    lb_launch_config best_cfg = orig;
+    lb_status st = LB_OK;
+    for (const auto& cf0 : cand) {
+        lb_launch_config cf = cf0;
+        if ((st = lb_set_launch_config(c, &cf))) break;
+        if ((st = run_steps(c, 2))) break;  // warm-up
+        HIP_TRY(hipEventRecord(c->ev0, c->stream));
+        if ((st = run_steps(c, trial_steps))) break;
+        HIP_TRY(hipEventRecord(c->ev1, c->stream));
+        HIP_TRY(hipEventSynchronize(c->ev1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        const double us = 1000.0 * ms / trial_steps;
+        if (us < best_us) {
+            best_us = us;
+            best_cfg = cf;
+        }
+    }
+    // graphs reduce launch gaps: keep them for the winner
+    best_cfg.graph_steps = 64;
+    // restore the state and time
+    HIP_TRY(hipMemcpyAsync(c->arena[cur0], backup, sizeof(float) * (size_t)c->L.arena_floats,
+                           hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    HIP_TRY(hipFree(backup));
+    c->cur = cur0;
+    c->t = t0;
+    if (st) {
+        lb_set_launch_config(c, &orig);
+        return st;
+    }
+    if ((st = lb_set_launch_config(c, &best_cfg))) return st;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[{c->model, size_class(c->L.fluid)}] = best_cfg;
+    }
+    if (best) *best = best_cfg;
+    if (us_per_step) *us_per_step = best_us;
+    c->timed_steps = 0;
+    return LB_OK;
+}
+
+void lb_free(lb_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    if (c->own_mem && c->mem) (void)hipFree(c->mem);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP32 populations against FP64):
+  - after 10^4 steps: max relative rho deviation <= 1e-4, max |dphi| <= 1e-4,
+    filled length within 0.5 lattice units (the acceptance gates);
+  - short runs (<= 500 steps) must agree much more tightly: 2e-5 relative on
+    rho, 2e-5 on phi, 1e-6 on u, which catches any wrong term long before the
+    accumulated FP32 rounding matters.
+"""
+import numpy as np
+import pytest
+
+from paper_0911_0459_amd import inputs as I
+from tests.helpers import field_errors, oracle_wall_grad, q_mid, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0911_0459_amd import lbcap
+    return lbcap
+
+
+def gpu_run(L, w, steps, sample_every=0, cfg=None, init=None, **over):
+    p = L.params_from_workload(w)           # the library maps the contact angle itself
+    for k, v in over.items():
+        setattr(p, k, v)
+    lat = L.Lattice(p, L.geometry_from_workload(w), w.initial_field() if init is None else init)
+    if cfg is not None:
+        lat.set_launch_config(**cfg)
+    ls = []
+    if sample_every:
+        for _ in range(steps // sample_every):
+            lat.step(sample_every)
+            ls.append(lat.interface_length()[1])
+        lat.step(steps - lat.t)
+    else:
+        lat.step(steps)
+    out = lat.moments()
+    lat.close()
+    return out, np.array(ls)
+
+
+def small_binary(nx=256, ny=64, H=20, ratio=10.0, seed=5, theta=60.0):
+    g = I.Geometry(nx=nx, ny=ny, x_in=nx // 2, tube_len=nx - nx // 2, tube_h=H, y0=(ny - H) // 2)
+    nl, ng = I.viscosity_pair(ratio)
+    return I.Workload(f"binary_{nx}x{ny}", "binary", g, steps=0, sample_every=0, seed=seed, nu_l=nl, nu_g=ng,
+                      theta_deg=theta, liquid=1.0, gas=-1.0, **I.BIN_CONSTS)
+
+
+# ---- the 10^4-step gates ---------------------------------------------------------
+def test_vdw_capillary_256x64_1e4_steps(L):
+    """Liquid-gas capillary 256x64 (H=20, length 128, tau 0.8, gradient -0.144)."""
+    w = I.vdw_capillary_256x64()
+    gpu, lg = gpu_run(L, w, 10_000, sample_every=500)
+    orc, lo = run_oracle(w, 10_000, sample_every=500)
+    drho, _, du = field_errors(w, gpu, orc)
+    print(f"vdw 1e4: max rel drho {drho:.3e}, max du {du:.3e}, max dl {np.abs(lg - lo).max():.3e}")
+    assert drho <= 1e-4
+    assert np.abs(lg - lo).max() <= 0.5
+    assert lo[-1] > lo[0]          # the tube is filling
+
+
+def test_binary_capillary_1e4_steps(L):
+    """Binary capillary (ratio 10, 60 degrees) on a 256x64 lattice."""
+    w = small_binary()
+    gpu, lg = gpu_run(L, w, 10_000, sample_every=500)
+    orc, lo = run_oracle(w, 10_000, sample_every=500)
+    drho, dphi, du = field_errors(w, gpu, orc)
+    print(f"binary 1e4: max rel drho {drho:.3e}, max dphi {dphi:.3e}, du {du:.3e}, "
+          f"max dl {np.abs(lg - lo).max():.3e}")
+    assert drho <= 1e-4 and dphi <= 1e-4
+    assert np.abs(lg - lo).max() <= 0.5
+
+
+# ---- tight short-run parity across tiles, tails and launch shapes --------------
+SHAPES = [
+    dict(tile_rows=1, schedule=0, persist_blocks_per_cu=4, graph_steps=0),
+    dict(tile_rows=2, schedule=1, persist_blocks_per_cu=4, graph_steps=2),
+    dict(tile_rows=4, schedule=2, persist_blocks_per_cu=4, graph_steps=64),
+    dict(tile_rows=8, schedule=1, persist_blocks_per_cu=4, graph_steps=16),
+]
+
+
+@pytest.mark.parametrize("cfg", SHAPES, ids=lambda c: f"ty{c['tile_rows']}s{c['schedule']}g{c['graph_steps']}")
+@pytest.mark.parametrize("model", ["vdw", "binary"])
+def test_ragged_lattice_short_run(L, model, cfg):
+    """150x37 lattice (ragged in x and y), odd tube height, several tiles."""
+    g = I.Geometry(nx=150, ny=37, x_in=53, tube_len=97, tube_h=13, y0=11)
+    if model == "vdw":
+        w = I.Workload("vdw_ragged", "vdw", g, 0, 0, seed=21, nu_l=0.13, nu_g=0.13, wall_grad=-0.1,
+                       liquid=4.5, gas=2.6, **I.VDW_CONSTS)
+    else:
+        nl, ng = I.viscosity_pair(30.0)
+        w = I.Workload("bin_ragged", "binary", g, 0, 0, seed=22, nu_l=nl, nu_g=ng, theta_deg=45.0,
+                       liquid=1.0, gas=-1.0, **I.BIN_CONSTS)
+    gpu, _ = gpu_run(L, w, 300, cfg=cfg)
+    orc, _ = run_oracle(w, 300)
+    drho, dphi, du = field_errors(w, gpu, orc)
+    assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (drho, dphi, du)
+
+
+def test_lambda_off_and_full_periodic_box(L):
+    """No walls at all (tube_len 0) and the Galilean term switched off."""
+    g = I.Geometry(nx=96, ny=40)
+    w = I.Workload("vdw_box", "vdw", g, 0, 0, seed=23, nu_l=0.2, nu_g=0.2, wall_grad=0.0, liquid=4.5,
+                   gas=2.6, **I.VDW_CONSTS)
+    y, x = np.mgrid[0:40, 0:96]
+    init = np.where(np.hypot(x - 48, y - 20) < 12, 4.5, 2.6) + I.node_noise(23, 96, 40)
+    for lam in (0, 1):
+        gpu, _ = gpu_run(L, w, 400, init=init, lambda_mode=lam)
+        orc, _ = run_oracle(w, 400, init=init, lambda_mode=lam)
+        drho, _, du = field_errors(w, gpu, orc)
+        assert drho < 2e-5 and du < 1e-6
+
+
+def test_poiseuille_body_force_narrow_lattice(L):
+    """nx = 3 (narrower than one tile) with the Guo body force."""
+    H = 20
+    g = I.Geometry(nx=3, ny=H + 2, x_in=0, tube_len=3, tube_h=H, y0=1)
+    w = I.Workload("pois", "binary", g, 0, 0, seed=24, nu_l=1 / 6, nu_g=1 / 6, wall_grad=0.0, liquid=1.0,
+                   gas=1.0, noise=0.0, **I.BIN_CONSTS)
+    init = np.ones((H + 2, 3))
+    gpu, _ = gpu_run(L, w, 3000, init=init, force_x=1e-5)
+    orc, _ = run_oracle(w, 3000, init=init, force_x=1e-5)
+    rho, ux, _, _ = gpu
+    assert np.abs(ux - orc[1]).max() / np.abs(orc[1]).max() < 1e-4
+    assert np.abs(rho - orc[0])[1:-1].max() < 1e-5
+
+
+def test_binary_1024x128_full_size_short(L):
+    """The 1024x128 binary workload at its real size, 300 steps, every node."""
+    w = I.binary_capillary_1024x128()
+    gw = oracle_wall_grad(w)
+    gpu, _ = gpu_run(L, w, 300)
+    orc, _ = run_oracle(w, 300)
+    drho, dphi, du = field_errors(w, gpu, orc)
+    assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6
+    assert abs(gw - (-0.236834)) < 1e-5
+
+
+def test_binary_4096x256_properties(L):
+    """The 4096x256 throughput lattice at its real size: conservation of mass
+    and order parameter, bounded phi, tube filling (no oracle run at this size)."""
+    w = I.binary_capillary_4096x256()
+    p = L.params_from_workload(w)
+    lat = L.Lattice(p, L.geometry_from_workload(w), w.initial_field())
+    rho0, _, _, phi0 = lat.moments()
+    l0 = lat.interface_length()[0]
+    lat.step(2000)
+    lat.check()
+    rho, ux, uy, phi = lat.moments()
+    fluid = ~w.geom.solid()
+    assert abs(rho[fluid].sum() - rho0[fluid].sum()) / rho0[fluid].sum() < 1e-5
+    assert abs(phi[fluid].sum() - phi0[fluid].sum()) / np.abs(phi0[fluid]).sum() < 1e-5
+    assert np.abs(phi[fluid]).max() < 1.1
+    assert lat.interface_length()[0] > l0
+    lat.close()
+
+
+# ---- determinism, checkpoints, batches -------------------------------------------
+def test_bitwise_determinism_and_launch_shape_independence(L):
+    w = small_binary(nx=200, ny=48, H=16)
+    a, _ = gpu_run(L, w, 200, cfg=SHAPES[0])
+    b, _ = gpu_run(L, w, 200, cfg=SHAPES[0])
+    c, _ = gpu_run(L, w, 200, cfg=SHAPES[2])
+    for x, y, z in zip(a, b, c):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_checkpoint_resume_is_bitwise(L):
+    w = small_binary(nx=200, ny=48, H=16)
+    p = L.params_from_workload(w, wall_grad=oracle_wall_grad(w))
+    g = L.geometry_from_workload(w)
+    ref = L.Lattice(p, g, w.initial_field())
+    ref.step(300)
+    full = ref.moments()
+    lat = L.Lattice(p, g, w.initial_field())
+    lat.step(120)
+    blob = lat.save()
+    lat.step(77)                     # wander off, then come back
+    lat.load(blob)
+    assert lat.t == 120
+    lat.step(180)
+    for x, y in zip(full, lat.moments()):
+        assert np.array_equal(x, y)
+    other = L.Lattice(p, L.make_geometry(210, 48, 100, 110, 16, 16), I.initial_field(
+        I.Geometry(210, 48, 100, 110, 16, 16), 1.0, -1.0, 0.5, 3))
+    with pytest.raises(L.LbError):
+        other.load(blob)
+
+
+def test_batch_equals_single_runs_and_oracle(L):
+    """Uneven capillaries advanced together give bitwise the single-run result."""
+    ws = [I.sweep_capillary(77, k, steps=0) for k in range(3)]
+    # shrink the draws so the oracle stays fast
+    ws = [I.Workload(w.name, w.model, I.Geometry(nx=96 + w.geom.tube_h * 2, ny=w.geom.tube_h + 12, x_in=96,
+                                                  tube_len=w.geom.tube_h * 2, tube_h=w.geom.tube_h, y0=6),
+                     0, 0, w.seed, nu_l=w.nu_l, nu_g=w.nu_g, theta_deg=w.theta_deg, liquid=1.0, gas=-1.0,
+                     **I.BIN_CONSTS) for w in ws]
+    P = [L.params_from_workload(w, wall_grad=oracle_wall_grad(w)) for w in ws]
+    G = [L.geometry_from_workload(w) for w in ws]
+    Q = [w.initial_field() for w in ws]
+    batch = L.Lattice(P, G, Q)
+    batch.step(250, sample_every=50)
+    for k, w in enumerate(ws):
+        single = L.Lattice(P[k], G[k], Q[k])
+        single.step(250)
+        for x, y in zip(batch.moments(k), single.moments()):
+            assert np.array_equal(x, y)
+        orc, lo = run_oracle(w, 250, sample_every=50)
+        drho, dphi, du = field_errors(w, batch.moments(k), orc)
+        assert drho < 2e-5 and dphi < 2e-5
+        steps, hist = batch.l_history(k)
+        assert list(steps) == [50, 100, 150, 200, 250]
+        assert np.abs(hist - lo).max() < 0.05
+    batch.close()
+
+
+def test_retire_freezes_and_revive_resumes(L):
+    ws = [small_binary(nx=160, ny=40, H=12, seed=s) for s in (31, 32)]
+    P = [L.params_from_workload(w, wall_grad=oracle_wall_grad(w)) for w in ws]
+    G = [L.geometry_from_workload(w) for w in ws]
+    Q = [w.initial_field() for w in ws]
+    b = L.Lattice(P, G, Q)
+    b.step(101)
+    frozen = b.moments(1)
+    b.retire(1)
+    b.step(51)
+    for x, y in zip(frozen, b.moments(1)):
+        assert np.array_equal(x, y)
+    b.revive(1)
+    b.step(99)
+    ref = L.Lattice(P[1], G[1], Q[1])
+    ref.step(200)
+    for x, y in zip(ref.moments(), b.moments(1)):
+        assert np.array_equal(x, y)
+    ref0 = L.Lattice(P[0], G[0], Q[0])
+    ref0.step(251)
+    for x, y in zip(ref0.moments(), b.moments(0)):
+        assert np.array_equal(x, y)
+
+
+def test_instability_is_reported(L):
+    """Density driven through the van der Waals pole: lb_check reports
+    LB_EUNSTABLE, as the oracle reports ORC_EUNSTABLE on the same input."""
+    g = I.Geometry(nx=16, ny=8)
+    q = np.full((8, 16), 3.0)
+    q[:, :8] = 10.4
+    p = L.make_params("vdw", kappa=0.02, nu_l=0.01)
+    lat = L.Lattice(p, L.make_geometry(16, 8), q)
+    lat.step(200)
+    with pytest.raises(L.LbError) as e:
+        lat.check()
+    assert e.value.code == L.LB_EUNSTABLE
+
+
+def test_autotune_keeps_state(L):
+    w = small_binary(nx=300, ny=64, H=24)
+    p = L.params_from_workload(w, wall_grad=oracle_wall_grad(w))
+    g = L.geometry_from_workload(w)
+    a = L.Lattice(p, g, w.initial_field())
+    a.step(40)
+    cfg, us = a.autotune(trial_steps=6)
+    assert cfg.tile_rows in (1, 2, 4, 8) and us > 0
+    assert a.t == 40
+    a.step(60)
+    b = L.Lattice(p, g, w.initial_field())
+    b.step(100)
+    for x, y in zip(a.moments(), b.moments()):
+        assert np.array_equal(x, y)
+
+
+def test_moments_device_matches_host(L):
+    import torch
+    w = small_binary(nx=130, ny=40, H=12)
+    lat = L.Lattice(L.params_from_workload(w, wall_grad=oracle_wall_grad(w)), L.geometry_from_workload(w),
+                    w.initial_field())
+    lat.step(37)
+    n = w.geom.nx * w.geom.ny
+    bufs = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(4)]
+    lat.moments_device(*bufs)
+    torch.cuda.synchronize()
+    host = lat.moments()
+    for d, h in zip(bufs, host):
+        assert np.array_equal(d.cpu().numpy().reshape(h.shape).astype(np.float64), h)

@@ -1,0 +1,130 @@
+"""CPU-side checks of the C-ABI library: exports, host-side maps, validation.
+
+These load liblbcap.so without a GPU: only entry points that do no device
+work are called.
+"""
+import math
+import re
+import os
+
+import numpy as np
+import pytest
+
+from oracle import Oracle, OracleError, OracleGeom, OracleParams
+from oracle import physics as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_0911_0459_amd.build import build_library
+    build_library(force=False)
+    from paper_0911_0459_amd import lbcap
+    return lbcap
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "lbcap.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b((?:lb|mlp)_[a-z_0-9]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol(L):
+    import ctypes
+    lib = ctypes.CDLL(L.LIB)
+    names = _declared_functions()
+    assert len(names) >= 30
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding binds every one of them
+    assert set(names) == set(L.EXPORTED)
+
+
+@pytest.mark.parametrize("theta", [30.0, 45.0, 60.0, 75.0, 90.0, 110.0, 135.0])
+def test_binary_wall_gradient_matches_cahn_quadrature(L, theta):
+    p = L.make_params("binary", kappa=0.04, A=0.04, B=0.04, nu_l=0.5, nu_g=0.05)
+    g_lib = L.lb_wall_gradient_for_angle(p, theta)
+    g_orc = P.binary_wall_gradient(theta, 0.04, 0.04, 0.04)
+    assert abs(g_lib - g_orc) < 1e-8
+
+
+def test_binary_wall_gradient_general_A_B(L):
+    """Bulk phases +-sqrt(A/B) when A != B: closed form vs quadrature."""
+    p = L.make_params("binary", kappa=0.03, A=0.05, B=0.02, nu_l=0.5, nu_g=0.05)
+    for theta in (40.0, 70.0, 120.0):
+        assert abs(L.lb_wall_gradient_for_angle(p, theta) -
+                   P.binary_wall_gradient(theta, 0.03, 0.05, 0.02)) < 1e-8
+
+
+@pytest.mark.parametrize("theta", [45.0, 60.0, 80.0, 100.0])
+def test_vdw_wall_gradient_matches_cahn_quadrature(L, theta):
+    p = L.make_params("vdw", kappa=0.02, nu_l=0.1)
+    g_lib = L.lb_wall_gradient_for_angle(p, theta)
+    g_orc = P.vdw_wall_gradient(theta)
+    assert abs(g_lib - g_orc) < 2e-6
+
+
+def test_vdw_sixty_degrees_near_paper_value(L):
+    """Sec. 2.2: a wall gradient of -0.144 gives 60 degrees."""
+    p = L.make_params("vdw", kappa=0.02, nu_l=0.1)
+    assert abs(L.lb_wall_gradient_for_angle(p, 60.0) - (-0.144)) < 0.005
+
+
+def test_vdw_coexistence_matches_maxwell(L):
+    p = L.make_params("vdw", kappa=0.02, nu_l=0.1)
+    rl, rg = L.lb_vdw_coexistence(p)
+    ol, og = P.vdw_maxwell()
+    assert abs(rl - ol) < 1e-9 and abs(rg - og) < 1e-9
+
+
+def test_unreachable_angles_rejected(L):
+    p = L.make_params("binary", kappa=0.04, A=0.04, B=0.04, nu_l=0.5, nu_g=0.05)
+    with pytest.raises(L.LbError) as e:
+        L.lb_wall_gradient_for_angle(p, 0.0)    # complete wetting is no contact angle
+    assert e.value.code == L.LB_EINVAL
+    with pytest.raises(L.LbError):
+        L.lb_wall_gradient_for_angle(p, 180.0)
+
+
+def _lib_init_code(L, p, g, q):
+    import ctypes as C
+    h = C.c_void_p()
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    return L._lib.lb_init(C.byref(h), C.byref(p), C.byref(g), q.ctypes.data_as(C.POINTER(C.c_double)),
+                          None, 0, None)
+
+
+@pytest.mark.parametrize("case", ["pole", "nu0", "nan", "thin", "outside"])
+def test_invalid_inputs_same_code_as_oracle(L, case):
+    """The library and the oracle reject the same invalid setups with the
+    same code (-1), before any device work."""
+    nx, ny = 20, 10
+    geo = dict(nx=nx, ny=ny)
+    q = np.full((ny, nx), 3.0)
+    vd = dict(kappa=0.02, nu_l=0.1)
+    if case == "pole":
+        q[:] = 11.0
+    elif case == "nu0":
+        vd["nu_l"] = 0.0
+    elif case == "nan":
+        q[3, 3] = math.nan
+    elif case == "thin":
+        geo = dict(nx=nx, ny=ny, x_in=5, tube_len=10, tube_h=2, y0=3)
+    elif case == "outside":
+        geo = dict(nx=nx, ny=ny, x_in=15, tube_len=10, tube_h=4, y0=3)
+    p = L.make_params("vdw", **vd)
+    rc = _lib_init_code(L, p, L.make_geometry(**geo), q)
+    with pytest.raises(OracleError) as e:
+        Oracle(OracleParams(model="vdw", **vd), OracleGeom(**geo), q)
+    assert rc == e.value.code == -1
+
+
+def test_state_bytes(L):
+    p = L.make_params("binary", kappa=0.04, nu_l=0.5, nu_g=0.05)
+    g = L.make_geometry(100, 30, 40, 60, 10, 10)
+    nb = L.lb_state_bytes(p, g)
+    # two arenas of 18 planes of 30 x 128 floats at least
+    assert nb >= 2 * 18 * 30 * 128 * 4
+    assert L.lb_state_bytes(p, L.make_geometry(100, 30, 40, 70, 10, 10)) == 0
