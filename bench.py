@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LUP = {"vdw": 72, "binary": 144}   # read + write of every stored FP32 population
+BYTES_PER_LUP = {"vdw": 72, "binary": 80}   # read + write of every stored FP32 value (9 f; binary + phi)
 
 
 def kernel_source_hash() -> str:
@@ -66,6 +66,23 @@ def build_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def copy_bandwidth(L, reps: int = 20, nbytes: int = 1 << 31):
+    """Read+write GB/s of the library's plain copy kernel on 2 GiB buffers."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    L.lb_stream_copy(b, a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        L.lb_stream_copy(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1000.0 * e0.elapsed_time(e1) / reps
+    return {"bytes_per_copy": 2 * nbytes, "us_per_copy": round(us, 1), "gbps": round(2 * nbytes / us / 1e3, 1)}
+
+
 def cpu_baseline(w, target_s: float = 15.0):
     """The FP64 oracle on one capillary of the workload, for a bounded number
     of steps (calibrated to about target_s seconds)."""
@@ -99,6 +116,10 @@ def main():
     ap.add_argument("--workload", default="sweep", choices=["sweep", "single4096", "single1024"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0, help="pin the launch shape (with --schedule)")
+    ap.add_argument("--schedule", type=int, default=-1)
+    ap.add_argument("--fp64-arith", type=int, default=-1)
+    ap.add_argument("--copy-probe", action="store_true", help="time the plain copy kernel only")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -110,6 +131,9 @@ def main():
     from paper_0911_0459_amd import lbcap as L
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        print(json.dumps({"copy_probe": copy_bandwidth(L, args.steps)}))
+        return
     works, config = build_workload(args.workload)
     model = works[0].model
     params = [L.params_from_workload(w) for w in works]
@@ -120,6 +144,11 @@ def main():
     if not args.no_autotune:
         cfg, _ = lat.autotune(trial_steps=10)
     cfg = lat.launch_config()
+    if args.tile_rows or args.schedule >= 0 or args.fp64_arith >= 0:
+        lat.set_launch_config(args.tile_rows or cfg.tile_rows, cfg.schedule if args.schedule < 0 else args.schedule,
+                              cfg.persist_blocks_per_cu, cfg.graph_steps,
+                              cfg.fp64_arith if args.fp64_arith < 0 else args.fp64_arith)
+        cfg = lat.launch_config()
     sample_every = config.get("sample_every", 0)
 
     lat.step(args.warmup)
@@ -161,6 +190,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": traffic,
             "kernel_us": round(us_kernel, 3),
+            "copy_kernel_gbps": copy_bandwidth(L, 10)["gbps"],
         },
         "cpu_baseline": None,
     }

@@ -203,16 +203,26 @@ int       lb_batch_size(const lb_ctx* c);
 long long lb_fluid_nodes(const lb_ctx* c);
 
 /* Launch configuration of the step kernel.
- *  tile_rows: rows per tile (1, 2, 4 or 8; tiles are 64 nodes wide).
- *  schedule: 0 one workgroup per tile in table order, 1 tiles grouped so that
- *    each of the 8 XCDs of the chip works on a contiguous run of tiles,
- *    2 persistent workgroups (grid = waves_per_cu x 256 CUs) striding the table.
- *  graph_steps: steps captured per HIP graph (even, >= 2; 0 = no graphs). */
+ *  schedule: 3 (default) row-sweep strips: one wavefront per strip of 62
+ *    output columns marching along y through chunks of chunk_rows rows (0: the
+ *    whole height), strips grouped so that each of the 8 XCDs works on a
+ *    contiguous run of them; every population row is read once per step.
+ *    0..2 tiles of 64 x tile_rows nodes with the order field recomputed on a
+ *    halo: 0 one workgroup per tile in table order, 1 tiles grouped per XCD,
+ *    2 persistent workgroups (persist_blocks_per_cu x 256 CUs) striding the table.
+ *  tile_rows: rows per tile for schedules 0..2 (1, 2, 4 or 8).
+ *  chunk_rows: rows per strip chunk for schedule 3 (0, 8, 16, 32 or 64).
+ *  graph_steps: steps captured per HIP graph (even, >= 2; 0 = no graphs).
+ *  fp64_arith: 1 evaluates the collision in FP64 (schedule 3; schedules 0..2
+ *    then compute the whole step in FP64), 0 in FP32.  The stored state is FP32
+ *    either way (same memory traffic). */
 typedef struct {
     int tile_rows;
     int schedule;
     int persist_blocks_per_cu;
     int graph_steps;
+    int fp64_arith;
+    int chunk_rows;
 } lb_launch_config;
 
 lb_status lb_get_launch_config(const lb_ctx* c, lb_launch_config* cfg);
@@ -228,6 +238,14 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
  * enqueued by the last lb_step / lb_batch_step call, measured with HIP events
  * on the context stream (0 if not available).  Synchronises. */
 lb_status lb_last_step_kernel_us(lb_ctx* c, double* us);
+
+/* Device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned
+ * pointers) by a plain grid-stride kernel with 16-byte loads and stores,
+ * enqueued on hip_stream.  Measurement infrastructure, not part of the
+ * method: it is the achievable-bandwidth reference for the step kernel's
+ * roofline and the kernel of known traffic that calibrates the HBM byte
+ * counters (its callers are the benchmark and the profiling runs). */
+lb_status lb_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 
 /* ---- learned l(t) surrogate: MLP 19 -> 256 -> 256 -> 256 -> 64, GELU ----
  * Hand-written HIP kernels for the forward pass, the backward pass and Adam

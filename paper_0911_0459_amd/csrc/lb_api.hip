@@ -4,10 +4,13 @@
 // single device allocation:
 //   [CapDev table][tile table][l_now][l history][history steps][history count]
 //   [health flags][population arena A][population arena B]
-// Every capillary owns a region of each arena: 9 FP32 planes of f and, for the
-// binary model, 9 planes of g, each plane ny x pitch with pitch = nx rounded up
-// to 64 floats.  Arena `cur` holds the post-collision populations of the
-// current time; a step pulls from it and writes the other arena.
+// Every capillary owns a region of each arena: 9 FP32 planes of shifted f and,
+// for the binary model, one plane of phi, each plane ny x pitch with pitch = nx
+// rounded up to 64 floats.  Capillary k reads arena (cur ^ par_k): it holds
+// f*(t) (and phi(t+1)); the other arena's phi plane holds phi(t).  A step
+// writes the other arena and flips cur.  Retiring a capillary drops its tiles
+// and freezes both arenas' regions; reviving it sets par_k so that it reads
+// the arena it was frozen in, with no copies.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -21,6 +24,7 @@
 #include "lbcap.h"
 #include "lb_internal.h"
 #include "lb_kernels.h"
+#include "lb_strip.h"
 #include "lb_thermo.h"
 
 using namespace lbk;
@@ -126,6 +130,8 @@ struct Layout {
     long long arena_floats = 0;
     long long fluid = 0;
     int max_tiles = 0;
+    int max_strips = 0;
+    size_t off_strips = 0;
     size_t off_caps, off_tiles, off_lnow, off_hist, off_hist_t, off_hist_n, off_flags, off_arena0, off_arena1,
         total;
 };
@@ -147,6 +153,30 @@ int count_tiles(const lb_geometry& g, int rows) {
             n += any;
         }
     return n;
+}
+
+// Strips of STRIP_OUT output columns; a strip lying entirely in the tube
+// section only covers the channel rows.  chunk = 0 keeps whole strips.
+void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk,
+                  std::vector<StripDev>* out, int* count) {
+    int n = 0;
+    if (out) out->clear();
+    for (size_t k = 0; k < G.size(); ++k) {
+        if (!active[k]) continue;
+        const lb_geometry& g = G[k];
+        for (int xs = 0; xs < g.nx; xs += STRIP_OUT) {
+            const int xe = std::min(xs + STRIP_OUT, g.nx);
+            const bool in_tube = g.tube_len > 0 && xs >= g.x_in && xe <= g.x_in + g.tube_len;
+            const int ya = in_tube ? g.y0 : 0;
+            const int yb = in_tube ? g.y0 + g.tube_h : g.ny;
+            const int step = chunk > 0 ? chunk : (yb - ya);
+            for (int y = ya; y < yb; y += step) {
+                if (out) out->push_back(StripDev{(int)k, xs, y, std::min(y + step, yb)});
+                ++n;
+            }
+        }
+    }
+    if (count) *count = n;
 }
 
 void build_tiles(const std::vector<lb_geometry>& G, const std::vector<int>& active, int rows,
@@ -190,10 +220,11 @@ lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L
         c.y0 = g.tube_len > 0 ? g.y0 : 0;
         c.y1 = g.tube_len > 0 ? g.y0 + g.tube_h : 0;
         c.active = 1;
+        c.par = 0;
         c.plane = (long long)g.ny * c.pitch;
         c.off_f = off;
-        c.off_g = off + 9 * c.plane;
-        off += (p.model == LB_BINARY ? 18 : 9) * c.plane;
+        c.off_phi = off + 9 * c.plane;
+        off += (p.model == LB_BINARY ? 10 : 9) * c.plane;
         c.kappa = (float)p.kappa;
         c.a = (float)p.a;
         c.b = (float)p.b;
@@ -212,16 +243,28 @@ lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L
         c.G = (float)G;
         c.Fx = (float)p.force_x;
         c.lam_on = (p.model == LB_VDW && p.lambda_mode == 0) ? 1.f : 0.f;
-        double qm = p.q_mid;
-        if (std::isnan(qm)) {
-            if (p.model == LB_BINARY) {
-                qm = 0.0;
-            } else {
-                double rl, rg;
-                qm = lbt::vdw_coexistence(p.a, p.b, p.T, &rl, &rg) ? 0.5 * (rl + rg) : 1.0 / (3.0 * p.b);
-            }
+        // vdW mid density: mean of the coexisting densities (critical density above Tc)
+        double mid = 0.0;
+        if (p.model == LB_VDW) {
+            double rl, rg;
+            mid = lbt::vdw_coexistence(p.a, p.b, p.T, &rl, &rg) ? 0.5 * (rl + rg) : 1.0 / (3.0 * p.b);
         }
+        const double qm = std::isnan(p.q_mid) ? mid : p.q_mid;
         c.q_mid = (float)qm;
+        // reference rest state of the shifted f storage
+        if (p.model == LB_VDW) {
+            const double rr = mid;
+            c.rho_ref = (float)rr;
+            c.X_ref = (float)(rr * p.T / (1.0 - p.b * rr) - p.a * rr * rr);
+            c.ibr = (float)(1.0 / (1.0 - p.b * (double)c.rho_ref));
+            c.phib2 = 0.f;
+        } else {
+            c.rho_ref = 1.f;
+            c.X_ref = (float)(1.0 / 3.0 + p.A * p.A / (4.0 * p.B));
+            c.ibr = 0.f;
+            c.phib2 = (float)(p.A / p.B);
+            c.phib = (float)std::sqrt(p.A / p.B);
+        }
         c.hist_off = k * LB_HISTORY_CAP;
         L.caps[k] = c;
         long long solid = g.tube_len > 0 ? (long long)g.tube_len * (g.ny - g.tube_h) : 0;
@@ -229,11 +272,18 @@ lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L
         L.max_tiles += count_tiles(g, 1);
     }
     L.arena_floats = off;
+    {
+        std::vector<lb_geometry> gv(G, G + n);
+        std::vector<int> all(n, 1);
+        build_strips(gv, all, 8, nullptr, &L.max_strips);   // the finest chunking allowed
+    }
     size_t o = 0;
     L.off_caps = o;
     o = align_up(o + sizeof(CapDev) * n);
     L.off_tiles = o;
     o = align_up(o + sizeof(TileDev) * (size_t)L.max_tiles);
+    L.off_strips = o;
+    o = align_up(o + sizeof(StripDev) * (size_t)L.max_strips);
     L.off_lnow = o;
     o = align_up(o + sizeof(float) * n);
     L.off_hist = o;
@@ -282,12 +332,14 @@ struct lb_ctx {
     std::vector<lb_geometry> G;
     Layout L;
     std::vector<int> active;
-    std::vector<int> frozen_buf;  // arena holding a retired capillary's state
+    std::vector<int> frozen_buf;  // read-arena of a retired capillary
     char* mem = nullptr;
     bool own_mem = false;
     CapDev* d_caps = nullptr;
     TileDev* d_tiles = nullptr;
     int ntiles = 0;
+    StripDev* d_strips = nullptr;
+    int nstrips = 0;
     float* d_lnow = nullptr;
     float* d_hist = nullptr;
     long long* d_hist_t = nullptr;
@@ -298,7 +350,7 @@ struct lb_ctx {
     bool own_stream = false;
     int cur = 0;
     long t = 0;
-    lb_launch_config cfg{4, 1, 4, 64};
+    lb_launch_config cfg{4, 3, 4, 64, 1, 0};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -325,24 +377,39 @@ lb_status upload_tiles(lb_ctx* c) {
     if (!tiles.empty())
         HIP_TRY(hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(), hipMemcpyHostToDevice,
                                c->stream));
+    std::vector<StripDev> strips;
+    build_strips(c->G, c->active, c->cfg.chunk_rows, &strips, nullptr);
+    if ((int)strips.size() > c->L.max_strips) return fail(LB_EINVAL, "strip table overflow");
+    c->nstrips = (int)strips.size();
+    if (!strips.empty())
+        HIP_TRY(hipMemcpyAsync(c->d_strips, strips.data(), sizeof(StripDev) * strips.size(), hipMemcpyHostToDevice,
+                               c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     drop_graphs(c);
     return LB_OK;
 }
 
-template <int MODEL, int TY, bool INIT>
+template <int MODEL, int TY, bool INIT, typename R>
 void launch_step_t(lb_ctx* c, const StepArgs& a, int grid) {
-    hipLaunchKernelGGL((lb_step_kernel<MODEL, TY, INIT>), dim3(grid), dim3(TILE_W, TY), 0, c->stream, a);
+    hipLaunchKernelGGL((lb_step_kernel<MODEL, TY, INIT, R>), dim3(grid), dim3(TILE_W, TY), 0, c->stream, a);
+}
+
+template <int MODEL, bool INIT, typename R>
+void launch_step_r(lb_ctx* c, const StepArgs& a, int grid) {
+    switch (c->cfg.tile_rows) {
+        case 1: launch_step_t<MODEL, 1, INIT, R>(c, a, grid); break;
+        case 2: launch_step_t<MODEL, 2, INIT, R>(c, a, grid); break;
+        case 8: launch_step_t<MODEL, 8, INIT, R>(c, a, grid); break;
+        default: launch_step_t<MODEL, 4, INIT, R>(c, a, grid); break;
+    }
 }
 
 template <int MODEL, bool INIT>
 void launch_step_m(lb_ctx* c, const StepArgs& a, int grid) {
-    switch (c->cfg.tile_rows) {
-        case 1: launch_step_t<MODEL, 1, INIT>(c, a, grid); break;
-        case 2: launch_step_t<MODEL, 2, INIT>(c, a, grid); break;
-        case 8: launch_step_t<MODEL, 8, INIT>(c, a, grid); break;
-        default: launch_step_t<MODEL, 4, INIT>(c, a, grid); break;
-    }
+    if (c->cfg.fp64_arith)
+        launch_step_r<MODEL, INIT, double>(c, a, grid);
+    else
+        launch_step_r<MODEL, INIT, float>(c, a, grid);
 }
 
 int grid_of(const lb_ctx* c) {
@@ -352,17 +419,51 @@ int grid_of(const lb_ctx* c) {
     return n;
 }
 
+template <int MODEL, typename CT>
+void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid) {
+    if (MODEL == 0)
+        hipLaunchKernelGGL((lb_strip_vdw<false, CT>), dim3(grid), dim3(SW), 0, c->stream, a);
+    else
+        hipLaunchKernelGGL((lb_strip_bin<false, CT>), dim3(grid), dim3(SW), 0, c->stream, a);
+}
+
 // Enqueue one step (or the initialisation when init is true) from arena cur.
 void enqueue_step(lb_ctx* c, bool init) {
     if (c->ntiles == 0) return;
+    if (!init && c->cfg.schedule == 3) {
+        if (c->nstrips == 0) return;
+        StripArgs a;
+        a.caps = c->d_caps;
+        a.strips = c->d_strips;
+        a.nstrips = c->nstrips;
+        a.xcd_group = 1;
+        a.arena0 = c->arena[0];
+        a.arena1 = c->arena[1];
+        a.cur = c->cur;
+        const int grid = 8 * ((c->nstrips + 7) / 8);
+        if (c->model == LB_VDW) {
+            if (c->cfg.fp64_arith)
+                launch_strip_t<0, double>(c, a, grid);
+            else
+                launch_strip_t<0, float>(c, a, grid);
+        } else {
+            if (c->cfg.fp64_arith)
+                launch_strip_t<1, double>(c, a, grid);
+            else
+                launch_strip_t<1, float>(c, a, grid);
+        }
+        return;
+    }
     StepArgs a;
     a.caps = c->d_caps;
     a.tiles = c->d_tiles;
     a.ntiles = c->ntiles;
     a.schedule = init ? 0 : c->cfg.schedule;
-    a.src = c->arena[init ? 1 : c->cur];
-    a.dst = c->arena[init ? 0 : c->cur ^ 1];
-    a.init_q = init ? c->arena[1] : nullptr;
+    a.arena0 = c->arena[0];
+    a.arena1 = c->arena[1];
+    // the initialisation reads the field uploaded into arena 1, writes arena 0
+    a.cur = init ? 1 : c->cur;
+    a.init = init ? 1 : 0;
     const int grid = init ? c->ntiles : grid_of(c);
     if (c->model == LB_VDW) {
         if (init)
@@ -469,6 +570,7 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
     }
     c->d_caps = (CapDev*)(c->mem + c->L.off_caps);
     c->d_tiles = (TileDev*)(c->mem + c->L.off_tiles);
+    c->d_strips = (StripDev*)(c->mem + c->L.off_strips);
     c->d_lnow = (float*)(c->mem + c->L.off_lnow);
     c->d_hist = (float*)(c->mem + c->L.off_hist);
     c->d_hist_t = (long long*)(c->mem + c->L.off_hist_t);
@@ -509,13 +611,17 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
         return bail(fail(LB_EDEVICE, "upload of descriptors failed"));
     s = upload_tiles(c);
     if (s) return bail(s);
-    // initial fields go to arena 1 as FP32, at each capillary's f offset
+    // initial fields go to arena 1 as FP32 planes (pitched): the phi plane for
+    // the binary model, plane 0 for vdW; that plane of arena 1 then holds
+    // phi(0) / is rewritten by the first step
     for (int k = 0; k < n; ++k) {
         const lb_geometry& g = G[k];
+        const CapDev& d = c->L.caps[k];
         std::vector<float> h((size_t)g.nx * g.ny);
         for (size_t i = 0; i < h.size(); ++i) h[i] = (float)init_q[k][i];
-        if (hipMemcpyAsync(c->arena[1] + c->L.caps[k].off_f, h.data(), sizeof(float) * h.size(),
-                           hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        float* dst = c->arena[1] + (c->model == LB_BINARY ? d.off_phi : d.off_f);
+        if (hipMemcpy2DAsync(dst, sizeof(float) * d.pitch, h.data(), sizeof(float) * g.nx, sizeof(float) * g.nx,
+                             g.ny, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess)
             return bail(fail(LB_EDEVICE, "upload of the initial field failed"));
     }
@@ -531,28 +637,30 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
     return LB_OK;
 }
 
-// Device region of capillary k in the arena that holds its state.
-float* state_of(lb_ctx* c, int k) { return c->arena[c->active[k] ? c->cur : c->frozen_buf[k]]; }
+// Arena capillary k reads (holds f*(t)); the other one holds phi(t).
+int buf_of(const lb_ctx* c, int k) { return c->active[k] ? (c->cur ^ c->L.caps[k].par) : c->frozen_buf[k]; }
 
 lb_status moments_into(lb_ctx* c, int k, float* rho, float* ux, float* uy, float* phi) {
-    const float* st = state_of(c, k);
+    const int b = buf_of(c, k);
+    const float* st = c->arena[b];
+    const float* prev = c->arena[b ^ 1];
     const long long n = (long long)c->G[k].nx * c->G[k].ny;
     const int grid = (int)std::min<long long>((n + 255) / 256, 4096);
     if (c->model == LB_VDW)
-        hipLaunchKernelGGL(lb_moments_kernel<0>, dim3(grid), dim3(256), 0, c->stream, c->d_caps, k, st, rho, ux,
-                           uy, phi);
+        hipLaunchKernelGGL(lb_moments_kernel<0>, dim3(grid), dim3(256), 0, c->stream, c->d_caps, k, st, prev, rho,
+                           ux, uy, phi);
     else
-        hipLaunchKernelGGL(lb_moments_kernel<1>, dim3(grid), dim3(256), 0, c->stream, c->d_caps, k, st, rho, ux,
-                           uy, phi);
+        hipLaunchKernelGGL(lb_moments_kernel<1>, dim3(grid), dim3(256), 0, c->stream, c->d_caps, k, st, prev, rho,
+                           ux, uy, phi);
     HIP_TRY(hipGetLastError());
     return LB_OK;
 }
 
 lb_status host_moments(lb_ctx* c, int k, double* rho, double* ux, double* uy, double* phi) {
     const long long n = (long long)c->G[k].nx * c->G[k].ny;
-    // scratch: the same capillary's region of the other arena (its fluid nodes
-    // are rewritten by the next step; a retired capillary's copy is not there)
-    float* scratch = c->arena[(c->active[k] ? c->cur : c->frozen_buf[k]) ^ 1] + c->L.caps[k].off_f;
+    // scratch: planes 0..3 of the capillary's f region in the arena it does
+    // not read (rewritten by its next step; that arena's phi plane is untouched)
+    float* scratch = c->arena[buf_of(c, k) ^ 1] + c->L.caps[k].off_f;
     float* out[4] = {scratch, scratch + n, scratch + 2 * n, scratch + 3 * n};
     lb_status s = moments_into(c, k, out[0], out[1], out[2], out[3]);
     if (s) return s;
@@ -576,9 +684,14 @@ lb_status host_moments(lb_ctx* c, int k, double* rho, double* ux, double* uy, do
 }
 
 lb_status launch_interface(lb_ctx* c, int record) {
-    hipLaunchKernelGGL(lb_interface_kernel, dim3(c->n), dim3(256), 0, c->stream, c->d_caps, c->n, c->model,
-                       c->arena[c->cur], c->d_lnow, c->d_hist, c->d_hist_t, c->d_hist_n, LB_HISTORY_CAP,
-                       (long long)c->t, record);
+    if (c->model == LB_VDW)
+        hipLaunchKernelGGL(lb_interface_kernel<0>, dim3(c->n), dim3(256), 0, c->stream, c->d_caps, c->n,
+                           c->arena[0], c->arena[1], c->cur, c->d_lnow, c->d_hist, c->d_hist_t, c->d_hist_n,
+                           LB_HISTORY_CAP, (long long)c->t, record);
+    else
+        hipLaunchKernelGGL(lb_interface_kernel<1>, dim3(c->n), dim3(256), 0, c->stream, c->d_caps, c->n,
+                           c->arena[0], c->arena[1], c->cur, c->d_lnow, c->d_hist, c->d_hist_t, c->d_hist_n,
+                           LB_HISTORY_CAP, (long long)c->t, record);
     HIP_TRY(hipGetLastError());
     return LB_OK;
 }
@@ -589,10 +702,10 @@ lb_status launch_health(lb_ctx* c) {
     // 512 threads: 8 rows of 64 (tiles have at most 8 rows)
     if (c->model == LB_VDW)
         hipLaunchKernelGGL(lb_health_kernel<0>, dim3(grid), dim3(512), 0, c->stream, c->d_caps, c->d_tiles,
-                           c->ntiles, c->arena[c->cur], c->d_flags);
+                           c->ntiles, c->arena[0], c->arena[1], c->cur, c->d_flags);
     else
         hipLaunchKernelGGL(lb_health_kernel<1>, dim3(grid), dim3(512), 0, c->stream, c->d_caps, c->d_tiles,
-                           c->ntiles, c->arena[c->cur], c->d_flags);
+                           c->ntiles, c->arena[0], c->arena[1], c->cur, c->d_flags);
     HIP_TRY(hipGetLastError());
     return LB_OK;
 }
@@ -602,22 +715,12 @@ lb_status cap_index(const lb_ctx* c, int cap) {
     return LB_OK;
 }
 
-// Copy capillary k's region (f, and g) between arenas.
-lb_status copy_region(lb_ctx* c, int k, int from, int to) {
-    const CapDev& d = c->L.caps[k];
-    const long long nf = (c->model == LB_BINARY ? 18 : 9) * d.plane;
-    HIP_TRY(hipMemcpyAsync(c->arena[to] + d.off_f, c->arena[from] + d.off_f, sizeof(float) * nf,
-                           hipMemcpyDeviceToDevice, c->stream));
-    return LB_OK;
-}
-
 lb_status set_active(lb_ctx* c, int k, int on) {
     if (c->active[k] == on) return LB_OK;
     if (!on) {
-        c->frozen_buf[k] = c->cur;
-    } else if (c->frozen_buf[k] != c->cur) {
-        lb_status s = copy_region(c, k, c->frozen_buf[k], c->cur);
-        if (s) return s;
+        c->frozen_buf[k] = c->cur ^ c->L.caps[k].par;
+    } else {
+        c->L.caps[k].par = c->cur ^ c->frozen_buf[k];
     }
     c->active[k] = on;
     c->L.caps[k].active = on;
@@ -625,9 +728,30 @@ lb_status set_active(lb_ctx* c, int k, int on) {
     return upload_tiles(c);
 }
 
+// Plain grid-stride copy with 16-byte accesses: the achievable-bandwidth
+// reference of the step kernel's roofline and the calibration kernel of the
+// HBM byte counters.
+__global__ void __launch_bounds__(256) lb_copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                      size_t n4) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 }  // namespace
 
 extern "C" {
+
+lb_status lb_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+    if (!dst || !src || bytes % 16 != 0 || ((uintptr_t)dst % 16) != 0 || ((uintptr_t)src % 16) != 0)
+        return fail(LB_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+    const size_t n4 = bytes / 16;
+    if (n4 == 0) return LB_OK;
+    const int grid = (int)std::min<size_t>((n4 + 255) / 256, 256 * 32);
+    hipLaunchKernelGGL(lb_copy_kernel, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream, (const float4*)src,
+                       (float4*)dst, n4);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
 
 const char* lb_last_error(void) { return g_err.c_str(); }
 
@@ -811,24 +935,40 @@ static uint64_t setup_hash(const lb_ctx* c) {
     return fnv1a(c->G.data(), sizeof(lb_geometry) * c->G.size(), h);
 }
 
-size_t lb_checkpoint_bytes(const lb_ctx* c) {
-    if (!c) return 0;
-    return sizeof(CkptHeader) + sizeof(int) * c->n + sizeof(float) * (size_t)c->L.arena_floats;
+// Floats of capillary k's region in one arena (f planes, and phi).
+static long long region_floats(const lb_ctx* c, int k) {
+    return (c->model == LB_BINARY ? 10 : 9) * c->L.caps[k].plane;
 }
 
+size_t lb_checkpoint_bytes(const lb_ctx* c) {
+    if (!c) return 0;
+    size_t floats = 0;
+    for (int k = 0; k < c->n; ++k)
+        floats += (size_t)region_floats(c, k) + (c->model == LB_BINARY ? (size_t)c->L.caps[k].plane : 0);
+    return sizeof(CkptHeader) + sizeof(int) * c->n + sizeof(float) * floats;
+}
+
+// Image: header, active flags, then per capillary its read-arena region
+// (f*(t), phi(t+1)) followed, for the binary model, by phi(t).
 lb_status lb_save(lb_ctx* c, void* host_buf, size_t bytes) {
     if (lb_status s = check_ctx(c)) return s;
     if (!host_buf || bytes < lb_checkpoint_bytes(c)) return fail(LB_EINVAL, "checkpoint buffer too small");
-    CkptHeader h{0x4C42434150434B31ULL, setup_hash(c), c->t, c->n, c->model, c->L.arena_floats};
+    CkptHeader h{0x4C42434150434B32ULL, setup_hash(c), c->t, c->n, c->model, c->L.arena_floats};
     char* p = (char*)host_buf;
     std::memcpy(p, &h, sizeof h);
     std::memcpy(p + sizeof h, c->active.data(), sizeof(int) * c->n);
     float* dst = (float*)(p + sizeof h + sizeof(int) * c->n);
     for (int k = 0; k < c->n; ++k) {
         const CapDev& d = c->L.caps[k];
-        const long long nf = (c->model == LB_BINARY ? 18 : 9) * d.plane;
-        HIP_TRY(hipMemcpyAsync(dst + d.off_f, state_of(c, k) + d.off_f, sizeof(float) * nf, hipMemcpyDeviceToHost,
-                               c->stream));
+        const int b = buf_of(c, k);
+        const long long nf = region_floats(c, k);
+        HIP_TRY(hipMemcpyAsync(dst, c->arena[b] + d.off_f, sizeof(float) * nf, hipMemcpyDeviceToHost, c->stream));
+        dst += nf;
+        if (c->model == LB_BINARY) {
+            HIP_TRY(hipMemcpyAsync(dst, c->arena[b ^ 1] + d.off_phi, sizeof(float) * d.plane, hipMemcpyDeviceToHost,
+                                   c->stream));
+            dst += d.plane;
+        }
     }
     HIP_TRY(hipStreamSynchronize(c->stream));
     return LB_OK;
@@ -839,20 +979,30 @@ lb_status lb_load(lb_ctx* c, const void* host_buf, size_t bytes) {
     if (!host_buf || bytes < lb_checkpoint_bytes(c)) return fail(LB_EINVAL, "checkpoint buffer too small");
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof h);
-    if (h.magic != 0x4C42434150434B31ULL || h.hash != setup_hash(c) || h.n != c->n || h.floats != c->L.arena_floats)
+    if (h.magic != 0x4C42434150434B32ULL || h.hash != setup_hash(c) || h.n != c->n || h.floats != c->L.arena_floats)
         return fail(LB_EINVAL, "checkpoint belongs to another setup");
     const char* p = (const char*)host_buf;
     std::vector<int> act(c->n);
     std::memcpy(act.data(), p + sizeof h, sizeof(int) * c->n);
     const float* src = (const float*)(p + sizeof h + sizeof(int) * c->n);
-    HIP_TRY(hipMemcpyAsync(c->arena[c->cur], src, sizeof(float) * c->L.arena_floats, hipMemcpyHostToDevice,
-                           c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    // every capillary reads arena cur after the load
     for (int k = 0; k < c->n; ++k) {
+        CapDev& d = c->L.caps[k];
+        const long long nf = region_floats(c, k);
+        HIP_TRY(hipMemcpyAsync(c->arena[c->cur] + d.off_f, src, sizeof(float) * nf, hipMemcpyHostToDevice,
+                               c->stream));
+        src += nf;
+        if (c->model == LB_BINARY) {
+            HIP_TRY(hipMemcpyAsync(c->arena[c->cur ^ 1] + d.off_phi, src, sizeof(float) * d.plane,
+                                   hipMemcpyHostToDevice, c->stream));
+            src += d.plane;
+        }
         c->active[k] = act[k] ? 1 : 0;
         c->frozen_buf[k] = c->cur;
-        c->L.caps[k].active = c->active[k];
+        d.par = 0;
+        d.active = c->active[k];
     }
+    HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpyAsync(c->d_caps, c->L.caps.data(), sizeof(CapDev) * c->n, hipMemcpyHostToDevice, c->stream));
     c->t = (long)h.t;
     c->unstable = 0;
@@ -869,12 +1019,16 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
     if (!c || !cfg) return fail(LB_EINVAL, "null argument");
     const int r = cfg->tile_rows;
     if (r != 1 && r != 2 && r != 4 && r != 8) return fail(LB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
-    if (cfg->schedule < 0 || cfg->schedule > 2) return fail(LB_EINVAL, "schedule must be 0, 1 or 2");
+    if (cfg->schedule < 0 || cfg->schedule > 3) return fail(LB_EINVAL, "schedule must be 0, 1, 2 or 3");
     if (cfg->schedule == 2 && (cfg->persist_blocks_per_cu < 1 || cfg->persist_blocks_per_cu > 32))
         return fail(LB_EINVAL, "persistent workgroups per CU must be in 1..32");
     if (cfg->graph_steps != 0 && (cfg->graph_steps < 2 || cfg->graph_steps % 2 != 0 || cfg->graph_steps > 4096))
         return fail(LB_EINVAL, "graph_steps must be 0 or an even number in 2..4096");
-    const bool retile = r != c->cfg.tile_rows;
+    if (cfg->fp64_arith != 0 && cfg->fp64_arith != 1) return fail(LB_EINVAL, "fp64_arith must be 0 or 1");
+    const int ch = cfg->chunk_rows;
+    if (ch != 0 && ch != 8 && ch != 16 && ch != 32 && ch != 64)
+        return fail(LB_EINVAL, "chunk_rows must be 0, 8, 16, 32 or 64");
+    const bool retile = r != c->cfg.tile_rows || cfg->chunk_rows != c->cfg.chunk_rows;
     c->cfg = *cfg;
     drop_graphs(c);
     if (retile) return upload_tiles(c);
@@ -884,20 +1038,21 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
 lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double* us_per_step) {
     if (lb_status s = check_ctx(c)) return s;
     if (trial_steps < 2) return fail(LB_EINVAL, "trial_steps must be >= 2");
-    // back up the current state: the trials advance the lattices
+    // back up both arenas: the trials advance the lattices
+    const size_t ab = sizeof(float) * (size_t)c->L.arena_floats;
     float* backup = nullptr;
-    HIP_TRY(hipMalloc(&backup, sizeof(float) * (size_t)c->L.arena_floats));
-    HIP_TRY(hipMemcpyAsync(backup, c->arena[c->cur], sizeof(float) * (size_t)c->L.arena_floats,
-                           hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMalloc(&backup, 2 * ab));
+    HIP_TRY(hipMemcpyAsync(backup, c->arena[0], ab, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync((char*)backup + ab, c->arena[1], ab, hipMemcpyDeviceToDevice, c->stream));
     const long t0 = c->t;
     const int cur0 = c->cur;
     const lb_launch_config orig = c->cfg;
     std::vector<lb_launch_config> cand;
-    for (int r : {1, 2, 4, 8}) {
-        cand.push_back({r, 0, 4, 0});
-        cand.push_back({r, 1, 4, 0});
-        cand.push_back({r, 2, 4, 0});
-        cand.push_back({r, 2, 8, 0});
+    const int ar = orig.fp64_arith;   // the arithmetic is a choice of the caller, not tuned
+    for (int ch : {0, 16, 32, 64}) cand.push_back({orig.tile_rows, 3, 4, 0, ar, ch});
+    for (int r : {4, 8}) {
+        cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
+        cand.push_back({r, 2, 4, 0, ar, orig.chunk_rows});
     }
     double best_us = 1e300;
     lb_launch_config best_cfg = orig;
@@ -921,8 +1076,8 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     // graphs reduce launch gaps: keep them for the winner
     best_cfg.graph_steps = 64;
     // restore the state and time
-    HIP_TRY(hipMemcpyAsync(c->arena[cur0], backup, sizeof(float) * (size_t)c->L.arena_floats,
-                           hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->arena[0], backup, ab, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->arena[1], (char*)backup + ab, ab, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipFree(backup));
     c->cur = cur0;

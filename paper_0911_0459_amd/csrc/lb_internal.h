@@ -9,14 +9,23 @@ namespace lbk {
 constexpr int TILE_W = 64;  // tile width along x = one wavefront
 
 // Per-capillary descriptor, resident in device memory.  Offsets are in floats
-// from the base of each population arena (the two arenas have identical layout).
+// from the base of each arena (the two arenas have identical layout).
+//
+// Stored per capillary and arena, each plane ny x pitch floats:
+//   planes 0..8   s_i = f_i - r_i, the shifted post-collision populations
+//   plane  9      phi (binary only): the order parameter
+// A step reads arena `cur ^ par` and writes the other one.  After step t the
+// read-from arena of the next step holds f*(t) and phi(t+1), and the other
+// arena's plane 9 still holds phi(t).
 struct CapDev {
     int nx, ny, pitch;       // lattice size; row pitch in floats (multiple of 64)
     int x_in, x_end;         // tube columns [x_in, x_end)
     int y0, y1;              // tube fluid rows [y0, y1)
     int active;              // 0: retired, not advanced
-    long long off_f;         // offset of f plane 0
-    long long off_g;         // offset of g plane 0 (binary)
+    int par;                 // this capillary reads arena cur ^ par
+    int pad1;
+    long long off_f;         // offset of plane 0
+    long long off_phi;       // offset of the phi plane (binary)
     long long plane;         // floats per plane = ny * pitch
     float kappa, a, b, T;    // vdW constants
     float A, B, Gamma;       // binary constants
@@ -26,11 +35,18 @@ struct CapDev {
     float Fx;                // body force
     float lam_on;            // 1: vdW Galilean lambda active
     float q_mid;             // interface level
+    // Reference rest state subtracted from the stored f populations:
+    // s_i = f_i - r_i with r the equilibrium at density rho_ref, u = 0, no
+    // gradients (r_0 = rho_ref - 5/3 X_ref, axis X_ref/3, diagonal X_ref/12).
+    float rho_ref;           // vdW: mid density; binary: 1
+    float X_ref;             // bulk pressure of the reference state
+    float ibr;               // vdW: 1/(1 - b rho_ref)
+    float phib2;             // binary: bulk phi^2 = A/B
     int hist_off;            // offset of this capillary's history in the history arrays
-    int pad0;
+    float phib;              // binary: bulk phi = sqrt(A/B)
 };
 
-// One tile: capillary index and tile origin.
+// One tile: capillary index, tile origin, number of rows inside the lattice.
 struct TileDev {
     int cap, x0, y0, rows;
 };
@@ -40,9 +56,10 @@ struct StepArgs {
     const TileDev* tiles;
     int ntiles;
     int schedule;            // 0 linear, 1 XCD-grouped, 2 persistent stride
-    const float* src;        // populations f*(t-1) (and g*)
-    float* dst;              // populations f*(t)
-    const float* init_q;     // INIT only: initial field of capillary k as ny*nx floats at caps[k].off_f
+    float* arena0;
+    float* arena1;
+    int cur;                 // capillary k reads arena (cur ^ par_k), writes the other
+    int init;                // 1: initialisation from the field in the read arena
 };
 
 }  // namespace lbk

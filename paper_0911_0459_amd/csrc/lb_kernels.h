@@ -3,15 +3,14 @@
 // One fused kernel performs a whole time step of the free-energy MRT scheme
 // (Eq. latbolt, Eq. latbolt2, Appendix A) for one 64 x TY tile of nodes:
 //
-//   pull streaming of f*(t-1) (and g*) with bounce-back from solid sources
+//   pull streaming of f*(t-1) with bounce-back from solid sources
 //   -> rest of boundary nodes (Sec. 2.2)
-//   -> moments rho, j, pxx, pxy (and phi)
-//   -> q = rho or phi into an LDS tile with a one-node halo; the halo values
-//      are recomputed from their own pulled populations
+//   -> moments rho, j, pxx, pxy
+//   -> the order field q (rho, or phi) in an LDS tile with a halo
 //   -> stencils of Eq. (best), wall ghosts for solid neighbours (wetting)
 //   -> bulk pressure, chemical potential, phi-dependent omega (Eq. nu)
 //   -> equilibrium moments in closed form -> MRT relaxation in moment space
-//   -> f*(t) = M^-1 m* written once per population (and g*(t) = g^eq).
+//   -> f*(t) = M^-1 m* written once per population.
 //
 // The 9x9 change of basis is done in registers: with the rates of Appendix A
 // only rho, j, pxx and pxy of the pre-collision state survive the collision
@@ -20,9 +19,25 @@
 // j (and qx, qy, which the collision discards), so it is applied in moment
 // space as j = 0.
 //
+// Binary model: every relaxation rate of g is 1 (Appendix A), so g after
+// collision is g^eq(phi, u, mu) of the node and is never stored.  Streaming
+// then gives phi(r, t+1) = sum_i g^eq_i(r - e_i, t) (g^eq_opp(i)(r, t) for a solid
+// source), which the kernel evaluates from phi, u and mu of the node and its
+// eight neighbours: phi is read with a two-node halo (the neighbours' mu needs
+// their Laplacian) and u of the one-node halo comes from the neighbours' own
+// pulled populations.  The update is formed as phi(t) plus the sum of the
+// small differences g^eq_i(r - e_i) - g^eq_i(r), so it is rounded once.
+//
 // Populations are SoA FP32 planes [9][ny][pitch], x fastest, pitch a multiple
 // of 64 floats; one wavefront covers one 64-wide row segment, so every load and
 // store of a population is a contiguous 256-byte access.
+//
+// FP32 storage keeps the accuracy of FP64 runs by storing f shifted by a
+// constant rest state: s_i = f_i - r_i, where r is the equilibrium of density
+// rho_ref at rest without gradients.  The reference carries density but no
+// momentum and no stress, so j, pxx and pxy are sums of the small s_i, and the
+// collision output is formed from differences to the reference (X - X_ref,
+// rho - rho_ref) without cancelling large numbers.
 #pragma once
 #include "lb_internal.h"
 
@@ -36,7 +51,17 @@ __host__ __device__ constexpr int ey_(int i) {
 }
 __host__ __device__ constexpr int opp_(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
-constexpr int W2 = TILE_W + 2;  // LDS row length (tile plus halo)
+constexpr int W2 = TILE_W + 2;  // LDS row: tile plus one-node halo
+constexpr int W4 = TILE_W + 4;  // LDS row: tile plus two-node halo
+
+template <int MODEL, int TY>
+struct Lds {
+    // vdW: q with a one-node halo.  Binary: phi with a two-node halo, then
+    // ux, uy and mu with a one-node halo.
+    static constexpr int PH = MODEL == 0 ? (TY + 2) * W2 : (TY + 4) * W4;
+    static constexpr int R1 = (TY + 2) * W2;
+    static constexpr int SIZE = MODEL == 0 ? PH : PH + 3 * R1;
+};
 
 struct Geo {
     int nx, ny, pitch, x_in, x_end, y0, y1;
@@ -62,11 +87,11 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// 3x3 neighbourhood of a fluid node: wrapped coordinates and solid flags,
-// indexed by D2Q9 direction d (neighbour r + e_d).
+// 3x3 neighbourhood of a node (wrapped coordinates): neighbour coordinates and
+// solid flags, bit d set when neighbour r + e_d is solid (d = 1..8).
 struct Hood {
     int xm, xp, ym, yp;
-    unsigned solid;  // bit d set when neighbour r + e_d is solid (d = 1..8)
+    unsigned solid;
 };
 
 __device__ __forceinline__ Hood hood_of(const Geo& g, int x, int y) {
@@ -78,217 +103,132 @@ __device__ __forceinline__ Hood hood_of(const Geo& g, int x, int y) {
     const bool cm = g.tube_col(h.xm), c0 = g.tube_col(x), cp = g.tube_col(h.xp);
     const bool rm = g.wall_row(h.ym), r0 = g.wall_row(y), rp = g.wall_row(h.yp);
     unsigned s = 0;
-    s |= (cp && r0) << 1;  // (1,0)
-    s |= (cm && r0) << 2;  // (-1,0)
-    s |= (c0 && rp) << 3;  // (0,1)
-    s |= (c0 && rm) << 4;  // (0,-1)
-    s |= (cp && rp) << 5;  // (1,1)
-    s |= (cm && rm) << 6;  // (-1,-1)
-    s |= (cm && rp) << 7;  // (-1,1)
-    s |= (cp && rm) << 8;  // (1,-1)
+    s |= (unsigned)(cp && r0) << 1;  // (1,0)
+    s |= (unsigned)(cm && r0) << 2;  // (-1,0)
+    s |= (unsigned)(c0 && rp) << 3;  // (0,1)
+    s |= (unsigned)(c0 && rm) << 4;  // (0,-1)
+    s |= (unsigned)(cp && rp) << 5;  // (1,1)
+    s |= (unsigned)(cm && rm) << 6;  // (-1,-1)
+    s |= (unsigned)(cm && rp) << 7;  // (-1,1)
+    s |= (unsigned)(cp && rm) << 8;  // (1,-1)
     h.solid = s;
     return h;
 }
 
-// Pull streaming of one population set at fluid node (x, y): direction i comes
-// from r - e_i, which is the neighbour in direction opp(i); a solid source is
-// replaced by the node's own opposite population (bounce-back).
+// Pull streaming of the f set at fluid node (x, y): direction i comes from
+// r - e_i, the neighbour in direction opp(i); a solid source is replaced by the
+// node's own opposite population (bounce-back).  Loads FP32, returns type R.
+template <typename R>
 __device__ __forceinline__ void pull9(const float* __restrict__ base, long long plane, const Geo& g,
-                                      const Hood& h, int x, int y, float (&f)[9]) {
+                                      const Hood& h, int x, int y, R (&f)[9]) {
     const long long own = (long long)y * g.pitch + x;
-    const int xs[3] = {h.xm, x, h.xp};
-    const int ys[3] = {h.ym, y, h.yp};
-    f[0] = base[own];
+    f[0] = (R)base[own];
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-        const int sx = xs[1 - ex_(i)], sy = ys[1 - ey_(i)];
+        const int sx = ex_(i) > 0 ? h.xm : (ex_(i) < 0 ? h.xp : x);
+        const int sy = ey_(i) > 0 ? h.ym : (ey_(i) < 0 ? h.yp : y);
         const bool bb = (h.solid >> opp_(i)) & 1u;
         const long long idx = bb ? (long long)opp_(i) * plane + own
                                  : (long long)i * plane + (long long)sy * g.pitch + sx;
-        f[i] = base[idx];
+        f[i] = (R)base[idx];
     }
 }
 
-__device__ __forceinline__ float sum9(const float (&f)[9]) {
-    // pairwise order, identical for every node
-    return ((f[0] + (f[1] + f[2])) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
+// Zeroth moment: the eight moving populations first (small), the rest
+// population last, so the result is rounded once at its own magnitude.
+template <typename R>
+__device__ __forceinline__ R sum9(const R (&f)[9]) {
+    return f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
 }
 
-// q of one LDS slot: sum of the pulled populations of the q-carrying set.
-__device__ __forceinline__ float slot_q(const float* __restrict__ qbase, long long plane, const Geo& g,
-                                        int x, int y) {
-    Hood h = hood_of(g, x, y);
-    float f[9];
-    pull9(qbase, plane, g, h, x, y, f);
-    return sum9(f);
+// Pre-collision moments of a pulled (shifted) population set; rest of boundary
+// nodes applied as j = 0.
+template <typename R>
+struct Mom {
+    R drho, jx, jy, pxx, pxy;
+};
+
+template <typename R>
+__device__ __forceinline__ Mom<R> moments_of(const R (&f)[9], bool bnd) {
+    Mom<R> m;
+    m.drho = sum9(f);
+    m.jx = ((f[1] - f[2]) + (f[5] - f[6])) + (f[8] - f[7]);
+    m.jy = ((f[3] - f[4]) + (f[5] - f[6])) + (f[7] - f[8]);
+    m.pxx = (f[1] + f[2]) - (f[3] + f[4]);
+    m.pxy = (f[5] + f[6]) - (f[7] + f[8]);
+    if (bnd) m.jx = m.jy = R(0);
+    return m;
 }
 
-template <int MODEL, int TY, bool INIT>
-__device__ __forceinline__ void step_tile(const StepArgs& a, int tile, float* qs) {
-    const TileDev t = a.tiles[tile];
-    const CapDev& c = a.caps[t.cap];
-    const Geo g = geo_of(c);
-    const long long P = c.plane;
-    const float* __restrict__ fsrc = a.src + c.off_f;
-    const float* __restrict__ gsrc = a.src + c.off_g;
-    const float* __restrict__ qsrc = MODEL == 0 ? fsrc : gsrc;
-    const int lx = threadIdx.x, ly = threadIdx.y;
-    const int tid = lx + TILE_W * ly;
-    const int x = t.x0 + lx, y = t.y0 + ly;
-    const bool own = (x < g.nx) && (y < g.ny) && c.active;
-    const int xw = x < g.nx ? x : wrap_mod(x, g.nx);
-    const int yw = y < g.ny ? y : wrap_mod(y, g.ny);
-    const bool fluid = !g.solid(xw, yw);
-
-    // ---- phase 1: own populations and q of every LDS slot -----------------
-    float f[9];
-    float qv = 0.f;
-    Hood h = hood_of(g, xw, yw);
-    if (fluid) {
-        if (INIT) {
-            qv = a.init_q[c.off_f + (long long)yw * g.nx + xw];
-        } else if (own) {
-            pull9(fsrc, P, g, h, xw, yw, f);
-            if (MODEL == 0) {
-                qv = sum9(f);
-            } else {
-                float gg[9];
-                pull9(gsrc, P, g, h, xw, yw, gg);
-                qv = sum9(gg);
-            }
-        } else {
-            qv = slot_q(qsrc, P, g, xw, yw);
-        }
-    }
-    qs[(ly + 1) * W2 + lx + 1] = qv;
-    constexpr int NH = 2 * W2 + 2 * TY;
-    for (int k = tid; k < NH; k += TILE_W * TY) {
-        int sx, sy;
-        if (k < W2) {
-            sx = k;
-            sy = 0;
-        } else if (k < 2 * W2) {
-            sx = k - W2;
-            sy = TY + 1;
-        } else {
-            const int m = k - 2 * W2;
-            sx = (m & 1) ? W2 - 1 : 0;
-            sy = 1 + (m >> 1);
-        }
-        const int gx = wrap_mod(t.x0 + sx - 1, g.nx);
-        const int gy = wrap_mod(t.y0 + sy - 1, g.ny);
-        float v = 0.f;
-        if (!g.solid(gx, gy)) {
-            if (INIT)
-                v = a.init_q[c.off_f + (long long)gy * g.nx + gx];
-            else
-                v = slot_q(qsrc, P, g, gx, gy);
-        }
-        qs[sy * W2 + sx] = v;
-    }
-    __syncthreads();
-    if (!(own && fluid)) return;
-
-    // ---- phase 2: collision of the own node -------------------------------
-    const unsigned sm = h.solid;
-    const bool bnd = sm != 0u;
-    float rho, jx, jy, pxx = 0.f, pxy = 0.f;
-    if (INIT) {
-        rho = MODEL == 0 ? qv : 1.f;
-        jx = jy = 0.f;
-    } else {
-        rho = MODEL == 0 ? qv : sum9(f);
-        jx = ((f[1] - f[2]) + (f[5] - f[6])) + (f[8] - f[7]);
-        jy = ((f[3] - f[4]) + (f[5] - f[6])) + (f[7] - f[8]);
-        pxx = (f[1] + f[2]) - (f[3] + f[4]);
-        pxy = (f[5] + f[6]) - (f[7] + f[8]);
-        if (bnd) jx = jy = 0.f;  // boundary node set to rest
-    }
-    const float F = bnd ? 0.f : c.Fx;
-
-    // stencils of Eq. (best) with wall ghosts (rule W)
-    const int cidx = (ly + 1) * W2 + lx + 1;
-    const float qc = qs[cidx];
-    float v1 = qs[cidx + 1], v2 = qs[cidx - 1], v3 = qs[cidx + W2], v4 = qs[cidx - W2];
-    float v5 = qs[cidx + W2 + 1], v6 = qs[cidx - W2 - 1], v7 = qs[cidx + W2 - 1], v8 = qs[cidx - W2 + 1];
-    if (bnd) {
-        const float G2 = 2.f * c.G;
-        // axis neighbours: mirror through the node
-        if (sm & (1u << 1)) v1 = qs[cidx - 1] - G2;
-        if (sm & (1u << 2)) v2 = qs[cidx + 1] - G2;
-        if (sm & (1u << 3)) v3 = qs[cidx - W2] - G2;
-        if (sm & (1u << 4)) v4 = qs[cidx + W2] - G2;
-        // diagonals: mirror across the wall that blocks them, else through the node
+// Stencils of Eq. (best) around LDS index ci (row stride RS) with the wall
+// ghost rule for solid neighbours: an axis neighbour is mirrored through the
+// node; a diagonal one is mirrored across the wall that blocks it (the x wall
+// first), or through the node at a convex corner; every ghost is lowered by
+// 2G so that the normal derivative at a flat wall is G.
+// The stencils are evaluated on the differences to the centre value, which are
+// small and exact for close neighbours, so no sum of large values cancels.
+template <int RS, typename R>
+__device__ __forceinline__ void stencil(const R* __restrict__ q, int ci, unsigned sm, R G2, R& dxq, R& dyq,
+                                        R& lapq) {
+    const R qc = q[ci];
+    R v1 = q[ci + 1] - qc, v2 = q[ci - 1] - qc, v3 = q[ci + RS] - qc, v4 = q[ci - RS] - qc;
+    R v5 = q[ci + RS + 1] - qc, v6 = q[ci - RS - 1] - qc, v7 = q[ci + RS - 1] - qc, v8 = q[ci - RS + 1] - qc;
+    if (sm) {
+        if (sm & (1u << 1)) v1 = (q[ci - 1] - qc) - G2;
+        if (sm & (1u << 2)) v2 = (q[ci + 1] - qc) - G2;
+        if (sm & (1u << 3)) v3 = (q[ci - RS] - qc) - G2;
+        if (sm & (1u << 4)) v4 = (q[ci + RS] - qc) - G2;
         // (dx, dy): the diagonal; dxi / dyi: direction indices of (dx,0) and (0,dy)
-        auto diag = [&](int dx, int dy, int dxi, int dyi) -> float {
-            if (sm & (1u << dxi)) return qs[cidx + dy * W2 - dx] - G2;
-            if (sm & (1u << dyi)) return qs[cidx - dy * W2 + dx] - G2;
-            return qs[cidx - dy * W2 - dx] - G2;
+        auto diag = [&](int dx, int dy, int dxi, int dyi) -> R {
+            if (sm & (1u << dxi)) return (q[ci + dy * RS - dx] - qc) - G2;
+            if (sm & (1u << dyi)) return (q[ci - dy * RS + dx] - qc) - G2;
+            return (q[ci - dy * RS - dx] - qc) - G2;
         };
         if (sm & (1u << 5)) v5 = diag(1, 1, 1, 3);
         if (sm & (1u << 6)) v6 = diag(-1, -1, 2, 4);
         if (sm & (1u << 7)) v7 = diag(-1, 1, 2, 3);
         if (sm & (1u << 8)) v8 = diag(1, -1, 1, 4);
     }
-    const float dxq = ((v5 + v8) - (v7 + v6) + 4.f * (v1 - v2)) * (1.f / 12.f);
-    const float dyq = ((v5 + v7) - (v8 + v6) + 4.f * (v3 - v4)) * (1.f / 12.f);
-    const float lapq = (((v5 + v6) + (v7 + v8)) + 4.f * ((v1 + v2) + (v3 + v4)) - 20.f * qc) * (1.f / 6.f);
+    dxq = ((v5 + v8) - (v7 + v6) + R(4) * (v1 - v2)) * (R(1) / R(12));
+    dyq = ((v5 + v7) - (v8 + v6) + R(4) * (v3 - v4)) * (R(1) / R(12));
+    lapq = (((v5 + v6) + (v7 + v8)) + R(4) * ((v1 + v2) + (v3 + v4))) * (R(1) / R(6));
+}
 
-    if (INIT) {
-        // moments of f^eq at u = 0: P_xx - P_yy and P_xy of Eq. (pt)
-        pxx = c.kappa * (dxq * dxq - dyq * dyq);
-        pxy = c.kappa * dxq * dyq;
-    }
+// Bulk part of the binary chemical potential, -A phi + B phi^3 = B phi (phi - phib)(phi + phib),
+// in the factored form that does not cancel near the bulk values.
+template <typename R>
+__device__ __forceinline__ R mu_bulk(const CapDev& c, R phi) {
+    return (R)c.B * phi * ((phi - (R)c.phib) * (phi + (R)c.phib));
+}
 
-    const float inv_rho = 1.f / rho;
-    const float ux = (jx + 0.5f * F) * inv_rho;
-    const float uy = jy * inv_rho;
-
-    // thermodynamics: X = p0 - kappa q lap q; lambda; omega
-    float X, lam = 0.f, omega, mu = 0.f, phi = 0.f;
-    if (MODEL == 0) {
-        const float ib = 1.f / (1.f - c.b * rho);
-        const float p0 = rho * c.T * ib - c.a * rho * rho;
-        X = p0 - c.kappa * rho * lapq;
-        omega = c.omega_l;
-        if (c.lam_on != 0.f) {
-            const float dp0 = c.T * ib * ib - 2.f * c.a * rho;
-            lam = (1.f / omega - 0.5f) * (1.f / 3.f - dp0);
-        }
-    } else {
-        phi = qc;
-        const float p2 = phi * phi;
-        const float p0 = rho * (1.f / 3.f) - 0.5f * c.A * p2 + 0.75f * c.B * p2 * p2;
-        X = p0 - c.kappa * phi * lapq;
-        mu = -c.A * phi + c.B * p2 * phi - c.kappa * lapq;
-        const float pc = fminf(fmaxf(phi, -1.f), 1.f);
-        const float nu = c.nu_g + 0.5f * (pc + 1.f) * (c.nu_l - c.nu_g);
-        omega = 2.f / (6.f * nu + 1.f);
-    }
-
-    // equilibrium moments in closed form (M f^eq with the Eq. equilibrium weights)
-    const float udq = ux * dxq + uy * dyq;
-    const float trQ = rho * (ux * ux + uy * uy) + 4.f * lam * udq;
-    const float dQ = rho * (ux * ux - uy * uy) + 2.f * lam * (ux * dxq - uy * dyq);
-    const float Qxy = rho * ux * uy + lam * (ux * dyq + uy * dxq);
-    const float grad2 = dxq * dxq + dyq * dyq;
-    const float pxx_eq = c.kappa * (dxq * dxq - dyq * dyq) + dQ;
-    const float pxy_eq = c.kappa * dxq * dyq + Qxy;
-
-    // relaxed moments (e, eps, qx, qy at equilibrium; shear modes at rate omega)
-    // plus the Guo source (I - S/2) M F in moment space
-    const float uF = ux * F;
-    float b = X * (1.f / 3.f) + trQ * (1.f / 12.f) + c.kappa * grad2 * (1.f / 12.f) + uF * (1.f / 12.f);
-    float d = X * (1.f / 12.f) + trQ * (1.f / 12.f) - c.kappa * grad2 * (1.f / 24.f) + uF * (1.f / 12.f);
-    const float hw = 1.f - 0.5f * omega;
-    const float pxs = pxx - omega * (pxx - pxx_eq) + hw * 2.f * uF;
-    const float pys = pxy - omega * (pxy - pxy_eq) + hw * (uy * F);
-    const float jxs = jx + F, jys = jy;
-    const float a7 = 0.25f * pxs, a8 = 0.25f * pys;
-    const float jx3 = jxs * (1.f / 3.f), jy3 = jys * (1.f / 3.f);
-    const float jpp = (jxs + jys) * (1.f / 12.f), jpm = (jxs - jys) * (1.f / 12.f);
-
-    float o[9];
+// MRT collision of one node in moment space (Appendix A rates, Guo source
+// (I - S/2) M F), returning the shifted post-collision populations.
+//   m:   pre-collision moments (rho - rho_ref, j after rest, pxx, pxy)
+//   dX:  X - X_ref, X = p0 - kappa q lap(q) the isotropic part of Eq. (equilibrium)
+//   lam: Galilean-term coefficient; dq: gradient of q; F: body force on this node
+template <typename R>
+__device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX, R lam, R omega,
+                                        R dxq, R dyq, R F, R (&o)[9]) {
+    const R kappa = (R)c.kappa;
+    const R udq = ux * dxq + uy * dyq;
+    const R trQ = rho * (ux * ux + uy * uy) + R(4) * lam * udq;
+    const R dQ = rho * (ux * ux - uy * uy) + R(2) * lam * (ux * dxq - uy * dyq);
+    const R Qxy = rho * ux * uy + lam * (ux * dyq + uy * dxq);
+    const R grad2 = dxq * dxq + dyq * dyq;
+    const R pxx_eq = kappa * (dxq * dxq - dyq * dyq) + dQ;
+    const R pxy_eq = kappa * dxq * dyq + Qxy;
+    const R uF = ux * F;
+    // common parts of the axis (b) and diagonal (d) populations minus their
+    // reference values X_ref/3 and X_ref/12 (e, eps at equilibrium plus source)
+    const R b = dX * (R(1) / R(3)) + (trQ + kappa * grad2 + uF) * (R(1) / R(12));
+    const R d = dX * (R(1) / R(12)) + (trQ - R(0.5) * kappa * grad2 + uF) * (R(1) / R(12));
+    const R hw = R(1) - R(0.5) * omega;
+    const R pxs = m.pxx - omega * (m.pxx - pxx_eq) + hw * R(2) * uF;
+    const R pys = m.pxy - omega * (m.pxy - pxy_eq) + hw * (uy * F);
+    const R jxs = m.jx + F, jys = m.jy;   // qx*, qy* = -jx*, -jy*
+    const R a7 = R(0.25) * pxs, a8 = R(0.25) * pys;
+    const R jx3 = jxs * (R(1) / R(3)), jy3 = jys * (R(1) / R(3));
+    const R jpp = (jxs + jys) * (R(1) / R(12)), jpm = (jxs - jys) * (R(1) / R(12));
     o[1] = b + jx3 + a7;
     o[2] = b - jx3 + a7;
     o[3] = b + jy3 - a7;
@@ -297,43 +237,309 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int tile, float* qs
     o[6] = d - jpp + a8;
     o[7] = d - jpm - a8;
     o[8] = d + jpm - a8;
-    o[0] = rho - 4.f * (b + d);
+    o[0] = m.drho - R(4) * (b + d);   // rest population minus rho_ref - 5/3 X_ref
+}
 
-    float* __restrict__ fdst = a.dst + c.off_f;
-    const long long own_idx = (long long)yw * g.pitch + xw;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fdst[(long long)i * P + own_idx] = o[i];
+// g^eq_i (i >= 1) of Appendix A from phi, u and Gamma mu.
+template <typename R>
+__device__ __forceinline__ R geq_i(int i, R phi, R ux, R uy, R gmu) {
+    const R eu = (R)ex_(i) * ux + (R)ey_(i) * uy;
+    const R w = i <= 4 ? R(1) / R(3) : R(1) / R(12);
+    return w * (gmu + phi * (eu + R(1.5) * eu * eu - R(0.5) * (ux * ux + uy * uy)));
+}
 
-    if (MODEL == 1) {
-        // g* = g^eq (all g rates are 1), Appendix A
-        const float Gm = c.Gamma * mu;
-        const float u2 = ux * ux + uy * uy;
-        const float base_ax = (1.f / 3.f) * (Gm - 0.5f * phi * u2);
-        const float base_dg = (1.f / 12.f) * (Gm - 0.5f * phi * u2);
-        float gq[9];
-        // axis: w = 1/3, e.u = +-ux / +-uy, 1.5 phi (e.u)^2 term
-        gq[1] = base_ax + (1.f / 3.f) * phi * (ux + 1.5f * ux * ux);
-        gq[2] = base_ax + (1.f / 3.f) * phi * (-ux + 1.5f * ux * ux);
-        gq[3] = base_ax + (1.f / 3.f) * phi * (uy + 1.5f * uy * uy);
-        gq[4] = base_ax + (1.f / 3.f) * phi * (-uy + 1.5f * uy * uy);
-        const float upp = ux + uy, upm = ux - uy;
-        gq[5] = base_dg + (1.f / 12.f) * phi * (upp + 1.5f * upp * upp);
-        gq[6] = base_dg + (1.f / 12.f) * phi * (-upp + 1.5f * upp * upp);
-        gq[7] = base_dg + (1.f / 12.f) * phi * (-upm + 1.5f * upm * upm);
-        gq[8] = base_dg + (1.f / 12.f) * phi * (upm + 1.5f * upm * upm);
-        gq[0] = phi - (5.f / 3.f) * Gm - (2.f / 3.f) * phi * u2;
-        float* __restrict__ gdst = a.dst + c.off_g;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) gdst[(long long)i * P + own_idx] = gq[i];
+// LDS slot (sx, sy) of the one-node ring around a 64 x TY tile, k < 2 W2 + 2 TY.
+template <int TY>
+__device__ __forceinline__ void ring_slot(int k, int& sx, int& sy) {
+    if (k < W2) {
+        sx = k;
+        sy = 0;
+    } else if (k < 2 * W2) {
+        sx = k - W2;
+        sy = TY + 1;
+    } else {
+        const int m = k - 2 * W2;
+        sx = (m & 1) ? W2 - 1 : 0;
+        sy = 1 + (m >> 1);
     }
 }
 
-template <int MODEL, int TY, bool INIT>
+struct TileCtx {
+    TileDev t;
+    const CapDev* c;
+    Geo g;
+    const float* src;
+    float* dst;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const StepArgs& a, int tile) {
+    TileCtx k;
+    k.t = a.tiles[tile];
+    k.c = &a.caps[k.t.cap];
+    k.g = geo_of(*k.c);
+    const int sb = a.cur ^ k.c->par;
+    k.src = sb ? a.arena1 : a.arena0;
+    k.dst = sb ? a.arena0 : a.arena1;
+    return k;
+}
+
+// ---- van der Waals liquid-gas model -----------------------------------------
+template <int TY, bool INIT, typename R>
+__device__ __forceinline__ void step_tile_vdw(const StepArgs& a, int tile, R* qs) {
+    const TileCtx k = tile_ctx(a, tile);
+    const CapDev& c = *k.c;
+    const Geo& g = k.g;
+    const long long P = c.plane;
+    const float* __restrict__ fsrc = k.src + c.off_f;
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int tid = lx + TILE_W * ly;
+    const int x = k.t.x0 + lx, y = k.t.y0 + ly;
+    const bool own = (x < g.nx) && (y < g.ny) && c.active;
+    const int xw = x < g.nx ? x : wrap_mod(x, g.nx);
+    const int yw = y < g.ny ? y : wrap_mod(y, g.ny);
+    const bool fluid = !g.solid(xw, yw);
+    const R rho_ref = (R)c.rho_ref;
+
+    // phase 1: drho of every LDS slot; own populations kept in registers
+    R f[9];
+    R qv = R(0);
+    const Hood h = hood_of(g, xw, yw);
+    if (fluid) {
+        if (INIT) {
+            qv = (R)fsrc[(long long)yw * g.pitch + xw] - rho_ref;
+        } else {
+            pull9(fsrc, P, g, h, xw, yw, f);
+            qv = sum9(f);
+        }
+    }
+    qs[(ly + 1) * W2 + lx + 1] = qv;
+    for (int r = tid; r < 2 * W2 + 2 * TY; r += TILE_W * TY) {
+        int sx, sy;
+        ring_slot<TY>(r, sx, sy);
+        const int gx = wrap_mod(k.t.x0 + sx - 1, g.nx);
+        const int gy = wrap_mod(k.t.y0 + sy - 1, g.ny);
+        R v = R(0);
+        if (!g.solid(gx, gy)) {
+            if (INIT) {
+                v = (R)fsrc[(long long)gy * g.pitch + gx] - rho_ref;
+            } else {
+                R ff[9];
+                pull9(fsrc, P, g, hood_of(g, gx, gy), gx, gy, ff);
+                v = sum9(ff);
+            }
+        }
+        qs[sy * W2 + sx] = v;
+    }
+    __syncthreads();
+    if (!(own && fluid)) return;
+
+    // phase 2: collision of the own node
+    const bool bnd = h.solid != 0u;
+    Mom<R> m;
+    if (INIT) {
+        m.drho = qv;
+        m.jx = m.jy = R(0);
+    } else {
+        m = moments_of(f, bnd);
+    }
+    const R F = bnd ? R(0) : (R)c.Fx;
+    const R kappa = (R)c.kappa;
+    R dxq, dyq, lapq;
+    stencil<W2>(qs, (ly + 1) * W2 + lx + 1, h.solid, R(2) * (R)c.G, dxq, dyq, lapq);
+    if (INIT) {
+        // f = f^eq at u = 0: its stress moments are those of Eq. (pt)
+        m.pxx = kappa * (dxq * dxq - dyq * dyq);
+        m.pxy = kappa * dxq * dyq;
+    }
+    const R rho = rho_ref + m.drho;
+    const R inv_rho = R(1) / rho;
+    const R ux = (m.jx + R(0.5) * F) * inv_rho;
+    const R uy = m.jy * inv_rho;
+    const R T = (R)c.T, av = (R)c.a;
+    const R ib = R(1) / (R(1) - (R)c.b * rho);
+    // p0(rho) - p0(rho_ref) = drho [T / ((1 - b rho)(1 - b rho_ref)) - a (rho + rho_ref)]
+    const R dX = m.drho * (T * ib * (R)c.ibr - av * (rho + rho_ref)) - kappa * rho * lapq;
+    const R omega = (R)c.omega_l;
+    R lam = R(0);
+    if (c.lam_on != 0.f) {
+        const R dp0 = T * ib * ib - R(2) * av * rho;
+        lam = (R(1) / omega - R(0.5)) * (R(1) / R(3) - dp0);
+    }
+    R o[9];
+    collide(c, m, rho, ux, uy, dX, lam, omega, dxq, dyq, F, o);
+    float* __restrict__ fdst = k.dst + c.off_f;
+    const long long own_idx = (long long)yw * g.pitch + xw;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fdst[(long long)i * P + own_idx] = (float)o[i];
+}
+
+// ---- binary model, g eliminated ----------------------------------------------
+// Velocity of a fluid node from its pulled populations (rest and force rules).
+template <typename R>
+__device__ __forceinline__ void node_u(const CapDev& c, const float* __restrict__ fsrc, const Geo& g, int x, int y,
+                                       bool init, R& ux, R& uy) {
+    const Hood h = hood_of(g, x, y);
+    const bool bnd = h.solid != 0u;
+    const R F = bnd ? R(0) : (R)c.Fx;
+    if (init) {
+        ux = R(0.5) * F / (R)c.rho_ref;
+        uy = R(0);
+        return;
+    }
+    R f[9];
+    pull9(fsrc, c.plane, g, h, x, y, f);
+    const Mom<R> m = moments_of(f, bnd);
+    const R inv_rho = R(1) / ((R)c.rho_ref + m.drho);
+    ux = (m.jx + R(0.5) * F) * inv_rho;
+    uy = m.jy * inv_rho;
+}
+
+template <int TY, bool INIT, typename R>
+__device__ __forceinline__ void step_tile_bin(const StepArgs& a, int tile, R* lds) {
+    R* PH = lds;                                  // phi, two-node halo, row W4
+    R* UX = lds + Lds<1, TY>::PH;                 // one-node halo, row W2
+    R* UY = UX + Lds<1, TY>::R1;
+    R* MU = UY + Lds<1, TY>::R1;
+    const TileCtx k = tile_ctx(a, tile);
+    const CapDev& c = *k.c;
+    const Geo& g = k.g;
+    const long long P = c.plane;
+    const float* __restrict__ fsrc = k.src + c.off_f;
+    const float* __restrict__ psrc = k.src + c.off_phi;
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int tid = lx + TILE_W * ly;
+    constexpr int NT = TILE_W * TY;
+    const int x = k.t.x0 + lx, y = k.t.y0 + ly;
+    const bool own = (x < g.nx) && (y < g.ny) && c.active;
+    const int xw = x < g.nx ? x : wrap_mod(x, g.nx);
+    const int yw = y < g.ny ? y : wrap_mod(y, g.ny);
+    const bool fluid = !g.solid(xw, yw);
+    const Hood h = hood_of(g, xw, yw);
+    const bool bnd = h.solid != 0u;
+    const R G2 = R(2) * (R)c.G;
+    const R kappa = (R)c.kappa, Gam = (R)c.Gamma;
+
+    // phase 1a: phi(t) on the tile and a two-node halo
+    for (int r = tid; r < (TY + 4) * W4; r += NT) {
+        const int sx = r % W4, sy = r / W4;
+        const int gx = wrap_mod(k.t.x0 + sx - 2, g.nx);
+        const int gy = wrap_mod(k.t.y0 + sy - 2, g.ny);
+        PH[r] = g.solid(gx, gy) ? R(0) : (R)psrc[(long long)gy * g.pitch + gx];
+    }
+    // phase 1b: own moments and u; u of the one-node ring
+    R f[9];
+    Mom<R> m{R(0), R(0), R(0), R(0), R(0)};
+    R ux = R(0), uy = R(0);
+    const R F = bnd ? R(0) : (R)c.Fx;
+    if (fluid) {
+        if (INIT) {
+            m.drho = R(1) - (R)c.rho_ref;
+        } else {
+            pull9(fsrc, P, g, h, xw, yw, f);
+            m = moments_of(f, bnd);
+        }
+        const R inv_rho = R(1) / ((R)c.rho_ref + m.drho);
+        ux = (m.jx + R(0.5) * F) * inv_rho;
+        uy = m.jy * inv_rho;
+    }
+    const int o1 = (ly + 1) * W2 + lx + 1;
+    UX[o1] = ux;
+    UY[o1] = uy;
+    for (int r = tid; r < 2 * W2 + 2 * TY; r += NT) {
+        int sx, sy;
+        ring_slot<TY>(r, sx, sy);
+        const int gx = wrap_mod(k.t.x0 + sx - 1, g.nx);
+        const int gy = wrap_mod(k.t.y0 + sy - 1, g.ny);
+        R vx = R(0), vy = R(0);
+        if (!g.solid(gx, gy)) node_u(c, fsrc, g, gx, gy, INIT, vx, vy);
+        UX[sy * W2 + sx] = vx;
+        UY[sy * W2 + sx] = vy;
+    }
+    __syncthreads();
+
+    // phase 2a: Gamma mu on the tile and its one-node ring (stencils of phi)
+    R dxq = R(0), dyq = R(0), lapq = R(0), phi = R(0);
+    const int o2 = (ly + 2) * W4 + lx + 2;
+    if (fluid) {
+        phi = PH[o2];
+        stencil<W4>(PH, o2, h.solid, G2, dxq, dyq, lapq);
+        MU[o1] = Gam * (mu_bulk(c, phi) - kappa * lapq);
+    } else {
+        MU[o1] = R(0);
+    }
+    for (int r = tid; r < 2 * W2 + 2 * TY; r += NT) {
+        int sx, sy;
+        ring_slot<TY>(r, sx, sy);
+        const int gx = wrap_mod(k.t.x0 + sx - 1, g.nx);
+        const int gy = wrap_mod(k.t.y0 + sy - 1, g.ny);
+        R v = R(0);
+        if (!g.solid(gx, gy)) {
+            const int pi = (sy + 1) * W4 + sx + 1;
+            R ddx, ddy, dl;
+            stencil<W4>(PH, pi, hood_of(g, gx, gy).solid, G2, ddx, ddy, dl);
+            v = Gam * (mu_bulk(c, PH[pi]) - kappa * dl);
+        }
+        MU[sy * W2 + sx] = v;
+    }
+    __syncthreads();
+    if (!(own && fluid)) return;
+
+    // phase 2b: collision of f
+    if (INIT) {
+        m.pxx = kappa * (dxq * dxq - dyq * dyq);
+        m.pxy = kappa * dxq * dyq;
+    }
+    const R rho = (R)c.rho_ref + m.drho;
+    const R p2 = phi * phi;
+    const R phib = (R)c.phib;
+    // p0 - X_ref = drho/3 + (B/4)(phi^2 - phib^2)(3 phi^2 + phib^2), X_ref = rho_ref/3 + A^2/(4B)
+    const R dX = m.drho * (R(1) / R(3)) + R(0.25) * (R)c.B * ((phi - phib) * (phi + phib)) * (R(3) * p2 + phib * phib) -
+                 kappa * phi * lapq;
+    const R pc = phi < R(-1) ? R(-1) : (phi > R(1) ? R(1) : phi);
+    const R nu_l = (R)c.nu_l, nu_g = (R)c.nu_g;
+    const R nu = nu_g + R(0.5) * (pc + R(1)) * (nu_l - nu_g);
+    const R omega = R(2) / (R(6) * nu + R(1));
+    R o[9];
+    collide(c, m, rho, ux, uy, dX, R(0), omega, dxq, dyq, F, o);
+    float* __restrict__ fdst = k.dst + c.off_f;
+    const long long own_idx = (long long)yw * g.pitch + xw;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fdst[(long long)i * P + own_idx] = (float)o[i];
+
+    // phase 2c: phi(t+1) = phi(t) + sum_i [g^eq_i(source of i) - g^eq_i(r)]
+    const R gmu = MU[o1];
+    R go[9];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) go[i] = geq_i(i, phi, ux, uy, gmu);
+    R delta = R(0);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+        R gin;
+        if ((h.solid >> opp_(i)) & 1u) {
+            gin = go[opp_(i)];   // bounce-back of g*_opp(i)(r)
+        } else {
+            const int s1 = o1 - ey_(i) * W2 - ex_(i);
+            const int s2 = o2 - ey_(i) * W4 - ex_(i);
+            gin = geq_i(i, PH[s2], UX[s1], UY[s1], MU[s1]);
+        }
+        delta += gin - go[i];
+    }
+    k.dst[c.off_phi + own_idx] = (float)(phi + delta);
+}
+
+// R: arithmetic type of the step (float, or double with FP32 storage).
+template <int MODEL, int TY, bool INIT, typename R>
 __global__ void __launch_bounds__(TILE_W* TY) lb_step_kernel(StepArgs a) {
-    __shared__ float qs[(TY + 2) * W2];
+    __shared__ R lds[Lds<MODEL, TY>::SIZE];
+    auto one = [&](int tile) {
+        if (MODEL == 0)
+            step_tile_vdw<TY, INIT, R>(a, tile, lds);
+        else
+            step_tile_bin<TY, INIT, R>(a, tile, lds);
+    };
     if (a.schedule == 2) {
         for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-            step_tile<MODEL, TY, INIT>(a, tile, qs);
+            one(tile);
             __syncthreads();
         }
     } else {
@@ -342,15 +548,17 @@ __global__ void __launch_bounds__(TILE_W* TY) lb_step_kernel(StepArgs a) {
             const int per = (a.ntiles + 7) >> 3;
             tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
         }
-        if (tile < a.ntiles) step_tile<MODEL, TY, INIT>(a, tile, qs);
+        if (tile < a.ntiles) one(tile);
     }
 }
 
 // ---- macroscopic fields of one capillary -----------------------------------
-// rho = sum f*, u = (j* - F/2)/rho (the collision added F to j), phi = sum g*.
+// rho = rho_ref + sum s*, u = (j* - F/2)/rho (the collision added F to j), phi(t)
+// from the phi plane of the other arena.
 template <int MODEL>
 __global__ void lb_moments_kernel(const CapDev* caps, int cap, const float* __restrict__ st,
-                                  float* rho_o, float* ux_o, float* uy_o, float* phi_o) {
+                                  const float* __restrict__ prev, float* rho_o, float* ux_o, float* uy_o,
+                                  float* phi_o) {
     const CapDev& c = caps[cap];
     const Geo g = geo_of(c);
     const long long n = (long long)g.nx * g.ny;
@@ -364,17 +572,13 @@ __global__ void lb_moments_kernel(const CapDev* caps, int cap, const float* __re
             float f[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[i] = st[c.off_f + i * c.plane + own];
-            r = sum9(f);
+            r = c.rho_ref + sum9(f);
             const float jx = ((f[1] - f[2]) + (f[5] - f[6])) + (f[8] - f[7]);
             const float jy = ((f[3] - f[4]) + (f[5] - f[6])) + (f[7] - f[8]);
             const float F = h.solid ? 0.f : c.Fx;
             u = (jx - 0.5f * F) / r;
             v = jy / r;
-            if (MODEL == 1) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) f[i] = st[c.off_g + i * c.plane + own];
-                p = sum9(f);
-            }
+            if (MODEL == 1) p = prev[c.off_phi + own];
         }
         if (rho_o) rho_o[k] = r;
         if (ux_o) ux_o[k] = u;
@@ -384,25 +588,31 @@ __global__ void lb_moments_kernel(const CapDev* caps, int cap, const float* __re
 }
 
 // ---- filled length of every capillary (one workgroup per capillary) --------
-__device__ __forceinline__ float centre_q(const CapDev& c, const float* __restrict__ st, int MODEL,
-                                          int x, int ya, int yb) {
-    const long long base = MODEL == 0 ? c.off_f : c.off_g;
+template <int MODEL>
+__device__ __forceinline__ float centre_q(const CapDev& c, const float* __restrict__ st,
+                                          const float* __restrict__ prev, int x, int ya, int yb) {
+    if (MODEL == 1)
+        return 0.5f * (prev[c.off_phi + (long long)ya * c.pitch + x] + prev[c.off_phi + (long long)yb * c.pitch + x]);
     float fa[9], fb[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        fa[i] = st[base + i * c.plane + (long long)ya * c.pitch + x];
-        fb[i] = st[base + i * c.plane + (long long)yb * c.pitch + x];
+        fa[i] = st[c.off_f + i * c.plane + (long long)ya * c.pitch + x];
+        fb[i] = st[c.off_f + i * c.plane + (long long)yb * c.pitch + x];
     }
-    return 0.5f * (sum9(fa) + sum9(fb));
+    return 0.5f * ((c.rho_ref + sum9(fa)) + (c.rho_ref + sum9(fb)));
 }
 
+template <int MODEL>
 __global__ void __launch_bounds__(256)
-lb_interface_kernel(const CapDev* caps, int ncap, int model, const float* __restrict__ st,
-                    float* l_now, float* hist, long long* hist_t, int* hist_n, int hist_cap,
-                    long long t_now, int record) {
+lb_interface_kernel(const CapDev* caps, int ncap, float* arena0, float* arena1, int cur, float* l_now,
+                    float* hist, long long* hist_t, int* hist_n, int hist_cap, long long t_now, int record) {
     const int cap = blockIdx.x;
     if (cap >= ncap) return;
     const CapDev& c = caps[cap];
+    if (!c.active) return;
+    const int sb = cur ^ c.par;
+    const float* st = sb ? arena1 : arena0;
+    const float* prev = sb ? arena0 : arena1;
     __shared__ int kmin_s;
     if (threadIdx.x == 0) kmin_s = 0x7fffffff;
     __syncthreads();
@@ -412,8 +622,7 @@ lb_interface_kernel(const CapDev* caps, int ncap, int model, const float* __rest
     const int yb = (H % 2 == 0) ? c.y0 + H / 2 : ya;
     int kmin = 0x7fffffff;
     for (int k = threadIdx.x; k < L; k += blockDim.x) {
-        const float q = centre_q(c, st, model, c.x_in + k, ya, yb);
-        if (q < c.q_mid) {
+        if (centre_q<MODEL>(c, st, prev, c.x_in + k, ya, yb) < c.q_mid) {
             kmin = k;
             break;  // later k of this thread are larger
         }
@@ -428,12 +637,12 @@ lb_interface_kernel(const CapDev* caps, int ncap, int model, const float* __rest
         else if (k == 0)
             l = 0.f;
         else {
-            const float qp = centre_q(c, st, model, c.x_in + k - 1, ya, yb);
-            const float qk = centre_q(c, st, model, c.x_in + k, ya, yb);
+            const float qp = centre_q<MODEL>(c, st, prev, c.x_in + k - 1, ya, yb);
+            const float qk = centre_q<MODEL>(c, st, prev, c.x_in + k, ya, yb);
             l = (float)(k - 1) + (qp - c.q_mid) / (qp - qk);
         }
         l_now[cap] = l;
-        if (record && c.active) {
+        if (record) {
             const int n = hist_n[cap];
             if (n < hist_cap) {
                 hist[(long long)c.hist_off + n] = l + 0.5f * (float)H;
@@ -444,19 +653,20 @@ lb_interface_kernel(const CapDev* caps, int ncap, int model, const float* __rest
     }
 }
 
-// ---- health scan: non-finite population or rho <= 0 -> flag per capillary ---
+// ---- health scan: non-finite value or rho <= 0 -> flag per capillary --------
 template <int MODEL>
-__global__ void lb_health_kernel(const CapDev* caps, const TileDev* tiles, int ntiles,
-                                 const float* __restrict__ st, int* flags) {
+__global__ void lb_health_kernel(const CapDev* caps, const TileDev* tiles, int ntiles, float* arena0,
+                                 float* arena1, int cur, int* flags) {
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const TileDev t = tiles[tile];
         const CapDev& c = caps[t.cap];
         const Geo g = geo_of(c);
+        const float* st = (cur ^ c.par) ? arena1 : arena0;
         for (int r = threadIdx.x / TILE_W; r < 8; r += blockDim.x / TILE_W) {
             const int x = t.x0 + (threadIdx.x % TILE_W), y = t.y0 + r;
             if (x >= g.nx || y >= g.ny || r >= t.rows || g.solid(x, y)) continue;
             const long long own = (long long)y * g.pitch + x;
-            float s = 0.f;
+            float s = c.rho_ref;
             bool bad = false;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
@@ -464,10 +674,7 @@ __global__ void lb_health_kernel(const CapDev* caps, const TileDev* tiles, int n
                 bad |= !isfinite(v);
                 s += v;
             }
-            if (MODEL == 1) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) bad |= !isfinite(st[c.off_g + i * c.plane + own]);
-            }
+            if (MODEL == 1) bad |= !isfinite(st[c.off_phi + own]);
             if (bad || !(s > 0.f)) atomicOr(&flags[t.cap], 1);
         }
     }

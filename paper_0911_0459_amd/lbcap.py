@@ -12,6 +12,9 @@ import math
 import os
 
 import numpy as np
+# PyTorch first: the library then binds to the HIP runtime PyTorch already
+# loaded (same soname), so both share one runtime and one device context.
+import torch  # noqa: F401
 
 from .build import LIB
 
@@ -46,7 +49,7 @@ class lb_geometry(C.Structure):
 
 class lb_launch_config(C.Structure):
     _fields_ = [("tile_rows", C.c_int), ("schedule", C.c_int), ("persist_blocks_per_cu", C.c_int),
-                ("graph_steps", C.c_int)]
+                ("graph_steps", C.c_int), ("fp64_arith", C.c_int), ("chunk_rows", C.c_int)]
 
     def asdict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -85,6 +88,7 @@ _SIGS = {
     "lb_set_launch_config": (C.c_int, [_vp, C.POINTER(lb_launch_config)]),
     "lb_autotune": (C.c_int, [_vp, C.c_int, C.POINTER(lb_launch_config), _dp]),
     "lb_last_step_kernel_us": (C.c_int, [_vp, _dp]),
+    "lb_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -151,6 +155,15 @@ def lb_vdw_coexistence(p: lb_params):
     l, g = C.c_double(), C.c_double()
     _check(_lib.lb_vdw_coexistence(C.byref(p), C.byref(l), C.byref(g)))
     return l.value, g.value
+
+
+def lb_stream_copy(dst, src, stream=None):
+    """Copy torch tensor src into dst (same byte size) with the library's copy kernel."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    s = torch.cuda.current_stream().cuda_stream if stream is None else stream
+    _check(_lib.lb_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, C.c_void_p(s)))
 
 
 def lb_state_bytes(p: lb_params, g: lb_geometry) -> int:
@@ -276,8 +289,9 @@ class Lattice:
         _check(_lib.lb_get_launch_config(self._h, C.byref(cfg)))
         return cfg
 
-    def set_launch_config(self, tile_rows=4, schedule=1, persist_blocks_per_cu=4, graph_steps=64):
-        cfg = lb_launch_config(tile_rows, schedule, persist_blocks_per_cu, graph_steps)
+    def set_launch_config(self, tile_rows=4, schedule=3, persist_blocks_per_cu=4, graph_steps=64, fp64_arith=1,
+                          chunk_rows=0):
+        cfg = lb_launch_config(tile_rows, schedule, persist_blocks_per_cu, graph_steps, fp64_arith, chunk_rows)
         _check(_lib.lb_set_launch_config(self._h, C.byref(cfg)))
 
     def autotune(self, trial_steps: int = 20):
