@@ -119,6 +119,7 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0, help="pin the launch shape (with --schedule)")
     ap.add_argument("--schedule", type=int, default=-1)
     ap.add_argument("--fp64-arith", type=int, default=-1)
+    ap.add_argument("--chunk-rows", type=int, default=-1)
     ap.add_argument("--copy-probe", action="store_true", help="time the plain copy kernel only")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -144,10 +145,11 @@ def main():
     if not args.no_autotune:
         cfg, _ = lat.autotune(trial_steps=10)
     cfg = lat.launch_config()
-    if args.tile_rows or args.schedule >= 0 or args.fp64_arith >= 0:
+    if args.tile_rows or args.schedule >= 0 or args.fp64_arith >= 0 or args.chunk_rows >= 0:
         lat.set_launch_config(args.tile_rows or cfg.tile_rows, cfg.schedule if args.schedule < 0 else args.schedule,
                               cfg.persist_blocks_per_cu, cfg.graph_steps,
-                              cfg.fp64_arith if args.fp64_arith < 0 else args.fp64_arith)
+                              cfg.fp64_arith if args.fp64_arith < 0 else args.fp64_arith,
+                              cfg.chunk_rows if args.chunk_rows < 0 else args.chunk_rows)
         cfg = lat.launch_config()
     sample_every = config.get("sample_every", 0)
 
@@ -183,7 +185,8 @@ def main():
         "config": config,
         "roofline": {
             "bound": "hbm",
-            "kernel": f"lb_step_kernel<{1 if model == 'binary' else 0},{cfg.tile_rows},false>",
+            "kernel": (f"lb_strip_{'bin' if model == 'binary' else 'vdw'}" if cfg.schedule == 3
+                       else f"lb_step_kernel<{1 if model == 'binary' else 0},{cfg.tile_rows}>"),
             "achieved": round(achieved, 1) if achieved else None,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -211,7 +211,7 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    halo: 0 one workgroup per tile in table order, 1 tiles grouped per XCD,
  *    2 persistent workgroups (persist_blocks_per_cu x 256 CUs) striding the table.
  *  tile_rows: rows per tile for schedules 0..2 (1, 2, 4 or 8).
- *  chunk_rows: rows per strip chunk for schedule 3 (0, 8, 16, 32 or 64).
+ *  chunk_rows: rows per strip chunk for schedule 3 (0, or 4..4096; default 8).
  *  graph_steps: steps captured per HIP graph (even, >= 2; 0 = no graphs).
  *  fp64_arith: 1 evaluates the collision in FP64 (schedule 3; schedules 0..2
  *    then compute the whole step in FP64), 0 in FP32.  The stored state is FP32

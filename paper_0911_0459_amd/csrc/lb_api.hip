@@ -157,6 +157,8 @@ int count_tiles(const lb_geometry& g, int rows) {
 
 // Strips of STRIP_OUT output columns; a strip lying entirely in the tube
 // section only covers the channel rows.  chunk = 0 keeps whole strips.
+constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
+
 void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk,
                   std::vector<StripDev>* out, int* count) {
     int n = 0;
@@ -275,7 +277,7 @@ lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L
     {
         std::vector<lb_geometry> gv(G, G + n);
         std::vector<int> all(n, 1);
-        build_strips(gv, all, 8, nullptr, &L.max_strips);   // the finest chunking allowed
+        build_strips(gv, all, LB_MIN_CHUNK, nullptr, &L.max_strips);   // the finest chunking allowed
     }
     size_t o = 0;
     L.off_caps = o;
@@ -350,7 +352,7 @@ struct lb_ctx {
     bool own_stream = false;
     int cur = 0;
     long t = 0;
-    lb_launch_config cfg{4, 3, 4, 64, 1, 0};
+    lb_launch_config cfg{4, 3, 4, 64, 1, 8};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -419,12 +421,12 @@ int grid_of(const lb_ctx* c) {
     return n;
 }
 
-template <int MODEL, typename CT>
+template <int MODEL, typename MT, typename CT, typename ST = CT>
 void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid) {
-    if (MODEL == 0)
-        hipLaunchKernelGGL((lb_strip_vdw<false, CT>), dim3(grid), dim3(SW), 0, c->stream, a);
+    if constexpr (MODEL == 0)
+        hipLaunchKernelGGL((lb_strip_vdw<CT>), dim3(grid), dim3(SW), 0, c->stream, a);
     else
-        hipLaunchKernelGGL((lb_strip_bin<false, CT>), dim3(grid), dim3(SW), 0, c->stream, a);
+        hipLaunchKernelGGL((lb_strip_bin<MT, CT, ST>), dim3(grid), dim3(SW), 0, c->stream, a);
 }
 
 // Enqueue one step (or the initialisation when init is true) from arena cur.
@@ -443,14 +445,15 @@ void enqueue_step(lb_ctx* c, bool init) {
         const int grid = 8 * ((c->nstrips + 7) / 8);
         if (c->model == LB_VDW) {
             if (c->cfg.fp64_arith)
-                launch_strip_t<0, double>(c, a, grid);
+                launch_strip_t<0, double, double>(c, a, grid);
             else
-                launch_strip_t<0, float>(c, a, grid);
+                launch_strip_t<0, float, float>(c, a, grid);
         } else {
+            // the collision's non-shear part in FP64 (the shear relaxation is exact enough in FP32)
             if (c->cfg.fp64_arith)
-                launch_strip_t<1, double>(c, a, grid);
+                launch_strip_t<1, float, double, float>(c, a, grid);
             else
-                launch_strip_t<1, float>(c, a, grid);
+                launch_strip_t<1, float, float, float>(c, a, grid);
         }
         return;
     }
@@ -1026,8 +1029,8 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
         return fail(LB_EINVAL, "graph_steps must be 0 or an even number in 2..4096");
     if (cfg->fp64_arith != 0 && cfg->fp64_arith != 1) return fail(LB_EINVAL, "fp64_arith must be 0 or 1");
     const int ch = cfg->chunk_rows;
-    if (ch != 0 && ch != 8 && ch != 16 && ch != 32 && ch != 64)
-        return fail(LB_EINVAL, "chunk_rows must be 0, 8, 16, 32 or 64");
+    if (ch != 0 && (ch < LB_MIN_CHUNK || ch > 4096))
+        return fail(LB_EINVAL, "chunk_rows must be 0 or in 4..4096");
     const bool retile = r != c->cfg.tile_rows || cfg->chunk_rows != c->cfg.chunk_rows;
     c->cfg = *cfg;
     drop_graphs(c);
@@ -1049,7 +1052,7 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     const lb_launch_config orig = c->cfg;
     std::vector<lb_launch_config> cand;
     const int ar = orig.fp64_arith;   // the arithmetic is a choice of the caller, not tuned
-    for (int ch : {0, 16, 32, 64}) cand.push_back({orig.tile_rows, 3, 4, 0, ar, ch});
+    for (int ch : {6, 8, 12, 16, 0}) cand.push_back({orig.tile_rows, 3, 4, 0, ar, ch});
     for (int r : {4, 8}) {
         cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
         cand.push_back({r, 2, 4, 0, ar, orig.chunk_rows});

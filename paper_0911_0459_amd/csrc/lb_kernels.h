@@ -206,37 +206,43 @@ __device__ __forceinline__ R mu_bulk(const CapDev& c, R phi) {
 //   m:   pre-collision moments (rho - rho_ref, j after rest, pxx, pxy)
 //   dX:  X - X_ref, X = p0 - kappa q lap(q) the isotropic part of Eq. (equilibrium)
 //   lam: Galilean-term coefficient; dq: gradient of q; F: body force on this node
-template <typename R>
+template <typename R, typename S = R>
 __device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX, R lam, R omega,
                                         R dxq, R dyq, R F, R (&o)[9]) {
     const R kappa = (R)c.kappa;
     const R udq = ux * dxq + uy * dyq;
     const R trQ = rho * (ux * ux + uy * uy) + R(4) * lam * udq;
-    const R dQ = rho * (ux * ux - uy * uy) + R(2) * lam * (ux * dxq - uy * dyq);
-    const R Qxy = rho * ux * uy + lam * (ux * dyq + uy * dxq);
     const R grad2 = dxq * dxq + dyq * dyq;
-    const R pxx_eq = kappa * (dxq * dxq - dyq * dyq) + dQ;
-    const R pxy_eq = kappa * dxq * dyq + Qxy;
+    // traceless stresses of the equilibrium and their relaxation in S
+    const S sux = (S)ux, suy = (S)uy, sdx = (S)dxq, sdy = (S)dyq, srho = (S)rho, slam = (S)lam;
+    const S dQ = srho * (sux * sux - suy * suy) + S(2) * slam * (sux * sdx - suy * sdy);
+    const S Qxy = srho * sux * suy + slam * (sux * sdy + suy * sdx);
+    const S pxx_eq = (S)c.kappa * (sdx * sdx - sdy * sdy) + dQ;
+    const S pxy_eq = (S)c.kappa * sdx * sdy + Qxy;
     const R uF = ux * F;
     // common parts of the axis (b) and diagonal (d) populations minus their
     // reference values X_ref/3 and X_ref/12 (e, eps at equilibrium plus source)
     const R b = dX * (R(1) / R(3)) + (trQ + kappa * grad2 + uF) * (R(1) / R(12));
     const R d = dX * (R(1) / R(12)) + (trQ - R(0.5) * kappa * grad2 + uF) * (R(1) / R(12));
     const R hw = R(1) - R(0.5) * omega;
-    const R pxs = m.pxx - omega * (m.pxx - pxx_eq) + hw * R(2) * uF;
-    const R pys = m.pxy - omega * (m.pxy - pxy_eq) + hw * (uy * F);
+    const R pxs = (R)((S)m.pxx - (S)omega * ((S)m.pxx - pxx_eq)) + hw * R(2) * uF;
+    const R pys = (R)((S)m.pxy - (S)omega * ((S)m.pxy - pxy_eq)) + hw * (uy * F);
     const R jxs = m.jx + F, jys = m.jy;   // qx*, qy* = -jx*, -jy*
     const R a7 = R(0.25) * pxs, a8 = R(0.25) * pys;
     const R jx3 = jxs * (R(1) / R(3)), jy3 = jys * (R(1) / R(3));
     const R jpp = (jxs + jys) * (R(1) / R(12)), jpm = (jxs - jys) * (R(1) / R(12));
-    o[1] = b + jx3 + a7;
-    o[2] = b - jx3 + a7;
-    o[3] = b + jy3 - a7;
-    o[4] = b - jy3 - a7;
-    o[5] = d + jpp + a8;
-    o[6] = d - jpp + a8;
-    o[7] = d - jpm - a8;
-    o[8] = d + jpm - a8;
+    // the even (common) part of each opposite pair is formed first and the
+    // small momentum term added last, so both members of a pair round at the
+    // same magnitude and their difference keeps the momentum
+    const R cx = b + a7, cy = b - a7, cp = d + a8, cm = d - a8;
+    o[1] = cx + jx3;
+    o[2] = cx - jx3;
+    o[3] = cy + jy3;
+    o[4] = cy - jy3;
+    o[5] = cp + jpp;
+    o[6] = cp - jpp;
+    o[7] = cm - jpm;
+    o[8] = cm + jpm;
     o[0] = m.drho - R(4) * (b + d);   // rest population minus rho_ref - 5/3 X_ref
 }
 

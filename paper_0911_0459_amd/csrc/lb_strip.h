@@ -42,48 +42,6 @@ struct StripArgs {
     int cur;
 };
 
-__device__ __forceinline__ int wrap_small(int v, int n) {
-    // |v - [0, n)| is at most a few rows/columns here
-    while (v < 0) v += n;
-    while (v >= n) v -= n;
-    return v;
-}
-
-// Pulled populations of node (x, y) (wrapped coordinates), or zeros for a solid node.
-struct Pulled {
-    float f[9];
-    unsigned solid;   // neighbour solid bits
-    bool fluid;
-};
-
-__device__ __forceinline__ void pull_node(const float* __restrict__ fs, long long P, const Geo& g, int x, int y,
-                                          Pulled& p) {
-    p.fluid = !g.solid(x, y);
-    const Hood h = hood_of(g, x, y);
-    p.solid = h.solid;
-    if (p.fluid) {
-        pull9(fs, P, g, h, x, y, p.f);
-    } else {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) p.f[i] = 0.f;
-    }
-}
-
-// Moments in CT, velocity u = (j + F/2)/rho after the rest rule.
-template <typename CT>
-__device__ __forceinline__ Mom<CT> moments_ct(const CapDev& c, const Pulled& p, CT& ux, CT& uy, CT& F) {
-    CT f[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = (CT)p.f[i];
-    const bool bnd = p.solid != 0u;
-    Mom<CT> m = moments_of(f, bnd);
-    F = bnd ? CT(0) : (CT)c.Fx;
-    const CT inv_rho = CT(1) / ((CT)c.rho_ref + m.drho);
-    ux = (m.jx + CT(0.5) * F) * inv_rho;
-    uy = m.jy * inv_rho;
-    return m;
-}
-
 // Stencils of Eq. (best) on three LDS rows (below, centre, above) at index j,
 // wall ghosts as in `stencil`.
 __device__ __forceinline__ void stencil3(const float* __restrict__ rm, const float* __restrict__ r0,
@@ -113,272 +71,360 @@ __device__ __forceinline__ void stencil3(const float* __restrict__ rm, const flo
     lapq = (((v5 + v6) + (v7 + v8)) + 4.f * ((v1 + v2) + (v3 + v4))) * (1.f / 6.f);
 }
 
+// Ordering of the LDS ring buffers between the lanes of the single wavefront
+// of a strip.  LDS instructions of one wavefront execute in program order, so
+// only the compiler must not move LDS accesses across this point; a workgroup
+// barrier would in addition wait for every outstanding global load, including
+// the row requested ahead of time.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int strip_index(const StripArgs& a) {
     if (!a.xcd_group) return blockIdx.x;
     const int per = (a.nstrips + 7) >> 3;
     return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
 }
 
+// Column data of one lane, fixed for the whole strip: the lane's column and its
+// two neighbours (periodic), and whether each lies in the tube section.
+struct LaneCols {
+    int c0, cm, cp;
+    bool t0, tm, tp;
+};
+
+__device__ __forceinline__ LaneCols lane_cols(const Geo& g, int xl) {
+    LaneCols L;
+    L.c0 = wrap_mod(xl, g.nx);
+    L.cm = L.c0 == 0 ? g.nx - 1 : L.c0 - 1;
+    L.cp = L.c0 == g.nx - 1 ? 0 : L.c0 + 1;
+    L.t0 = g.tube_col(L.c0);
+    L.tm = g.tube_col(L.cm);
+    L.tp = g.tube_col(L.cp);
+    return L;
+}
+
+// Row data: wrapped row and neighbours, their offsets, whether they are wall rows.
+struct RowInfo {
+    int y0, ym, yp;
+    bool w0, wm, wp;
+    bool any;   // some wall row among ym, y0, yp (same for every lane)
+};
+
+__device__ __forceinline__ RowInfo row_info(const Geo& g, int y) {
+    RowInfo r;
+    r.y0 = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+    r.ym = r.y0 == 0 ? g.ny - 1 : r.y0 - 1;
+    r.yp = r.y0 == g.ny - 1 ? 0 : r.y0 + 1;
+    r.w0 = g.wall_row(r.y0);
+    r.wm = g.wall_row(r.ym);
+    r.wp = g.wall_row(r.yp);
+    r.any = r.w0 || r.wm || r.wp;
+    return r;
+}
+
+// Solid-neighbour bits of the lane's node on this row (bit d: r + e_d solid).
+__device__ __forceinline__ unsigned solid_bits(const LaneCols& L, const RowInfo& r) {
+    return ((unsigned)(L.tp && r.w0) << 1) | ((unsigned)(L.tm && r.w0) << 2) | ((unsigned)(L.t0 && r.wp) << 3) |
+           ((unsigned)(L.t0 && r.wm) << 4) | ((unsigned)(L.tp && r.wp) << 5) | ((unsigned)(L.tm && r.wm) << 6) |
+           ((unsigned)(L.tm && r.wp) << 7) | ((unsigned)(L.tp && r.wm) << 8);
+}
+
+// Pull of the lane's node on a row (bounce-back for solid sources).  Straight-line
+// code, the source chosen by selects: a branch around the loads (even a uniform
+// one) makes the compiler's wait counting assume the path without them, so
+// that every later use of an older load would wait for these ones as well.
+__device__ __forceinline__ void pull_lane(const float* __restrict__ fs, int P, int pitch, const LaneCols& L,
+                                          const RowInfo& r, unsigned sm, float (&f)[9]) {
+    const int o0 = r.y0 * pitch, om = r.ym * pitch, op = r.yp * pitch;
+    const int own = o0 + L.c0;
+    auto src = [&](int i, int off) -> int {
+        return ((sm >> opp_(i)) & 1u) ? opp_(i) * P + own : i * P + off;
+    };
+    f[0] = fs[own];
+    f[1] = fs[src(1, o0 + L.cm)];
+    f[2] = fs[src(2, o0 + L.cp)];
+    f[3] = fs[src(3, om + L.c0)];
+    f[4] = fs[src(4, op + L.c0)];
+    f[5] = fs[src(5, om + L.cm)];
+    f[6] = fs[src(6, op + L.cp)];
+    f[7] = fs[src(7, om + L.cp)];
+    f[8] = fs[src(8, op + L.cm)];
+}
+
 // ---- binary model --------------------------------------------------------------
-template <bool INIT, typename CT>
+// Reads f*(t-1) and phi(t) of one strip chunk, writes f*(t) and phi(t+1).
+template <typename MT, typename CT, typename ST = CT>
 __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
     const int si = strip_index(a);
     if (si >= a.nstrips) return;
     const StripDev s = a.strips[si];
-    const CapDev& c = a.caps[s.cap];
+    // by value: one scalar load at entry, kept in registers (a reference would be
+    // re-read from memory after every global store of the loop)
+    const CapDev c = a.caps[s.cap];
     const Geo g = geo_of(c);
-    const long long P = c.plane;
+    const int P = (int)c.plane;
     const int sb = a.cur ^ c.par;
-    const float* __restrict__ src = sb ? a.arena1 : a.arena0;
-    float* __restrict__ dst = sb ? a.arena0 : a.arena1;
-    const float* __restrict__ fs = src + c.off_f;
-    const float* __restrict__ ps = src + c.off_phi;
-    float* __restrict__ fd = dst + c.off_f;
-    float* __restrict__ pd = dst + c.off_phi;
+    const float* __restrict__ fs = (sb ? a.arena1 : a.arena0) + c.off_f;
+    const float* __restrict__ ps = (sb ? a.arena1 : a.arena0) + c.off_phi;
+    float* __restrict__ fd = (sb ? a.arena0 : a.arena1) + c.off_f;
+    float* __restrict__ pd = (sb ? a.arena0 : a.arena1) + c.off_phi;
 
-    __shared__ float PH[5][PHW];      // phi rows, column xs-2+j at index j
-    __shared__ float UX[3][SW], UY[3][SW], MU[3][SW];   // column xs-1+k at lane k
+    __shared__ float PH[5][PHW];                         // phi rows, column xs-2+j at index j
+    // column xs-1+k at lane k: velocity and Gamma mu - phi |u|^2 / 2, the part of g^eq
+    // that does not depend on the direction
+    __shared__ float UX[3][SW], UY[3][SW], AM[3][SW];
 
     const int k = threadIdx.x;
-    const int xl = s.xs + k - 1;                 // lane column (unwrapped)
-    const int col = wrap_small(xl, g.nx);
+    const int xl = s.xs + k - 1;
+    const LaneCols L = lane_cols(g, xl);
     const bool out_col = k >= 1 && k <= STRIP_OUT && xl < g.nx;
+    // the two extra phi columns, xs-2 (lane 0) and xs+63 (lane 1)
+    const int ce = wrap_mod(k == 0 ? s.xs - 2 : s.xs + SW - 1, g.nx);
+    const bool te = g.tube_col(ce);
     const float G2 = 2.f * c.G;
     const float kap = c.kappa, Gam = c.Gamma;
-    auto slot5 = [&](int y) { return (y - s.ya + 10) % 5; };
-    auto slot3 = [&](int y) { return (y - s.ya + 9) % 3; };
 
-    auto load_phi_row = [&](int y, float& main, float& extra) {
-        const int yw = wrap_small(y, g.ny);
-        main = g.solid(col, yw) ? 0.f : ps[(long long)yw * g.pitch + col];
-        extra = 0.f;
-        if (k < 2) {
-            const int xe = wrap_small(k == 0 ? s.xs - 2 : s.xs + SW - 1, g.nx);
-            extra = g.solid(xe, yw) ? 0.f : ps[(long long)yw * g.pitch + xe];
-        }
+    // phi loads are issued unconditionally (solid nodes have valid addresses) and
+    // masked when stored, so that no instruction waits on them early
+    const int cx = k < 2 ? ce : L.c0;
+    auto phi_load = [&](const RowInfo& r, float& m, float& e) {
+        m = ps[r.y0 * g.pitch + L.c0];
+        e = ps[r.y0 * g.pitch + cx];
     };
-    auto store_phi_row = [&](int y, float main, float extra) {
-        float* r = PH[slot5(y)];
-        r[k + 1] = main;
-        if (k == 0) r[0] = extra;
-        if (k == 1) r[PHW - 1] = extra;
+    auto phi_store = [&](int sl, const RowInfo& r, float m, float e) {
+        PH[sl][k + 1] = (L.t0 && r.w0) ? 0.f : m;
+        if (k == 0) PH[sl][0] = (te && r.w0) ? 0.f : e;
+        if (k == 1) PH[sl][PHW - 1] = (te && r.w0) ? 0.f : e;
     };
-    auto pull_row = [&](int y, Pulled& p) {
-        if (INIT) {
-            const int yw = wrap_small(y, g.ny);
-            p.fluid = !g.solid(col, yw);
-            p.solid = hood_of(g, col, yw).solid;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) p.f[i] = 0.f;   // f = f^eq at u = 0, rho = 1
+    // moments of a pulled row (FP32, kept by the caller) and its velocity into LDS
+    auto u_row = [&](int sl, const float (&f)[9], bool fluid, unsigned sm, Mom<float>& m) {
+        float ux = 0.f, uy = 0.f;
+        if (fluid) {
+            const bool bnd = sm != 0u;
+            m = moments_of(f, bnd);
+            const float F = bnd ? 0.f : c.Fx;
+            const float inv_rho = 1.f / (c.rho_ref + m.drho);
+            ux = (m.jx + 0.5f * F) * inv_rho;
+            uy = m.jy * inv_rho;
         } else {
-            pull_node(fs, P, g, col, wrap_small(y, g.ny), p);
+            m = Mom<float>{0.f, 0.f, 0.f, 0.f, 0.f};
         }
+        UX[sl][k] = ux;
+        UY[sl][k] = uy;
     };
-    // u of a pulled row into the ring (float), moments kept by the caller
-    auto put_u = [&](int y, const Pulled& p, Mom<CT>& m, CT& ux, CT& uy, CT& F) {
-        if (p.fluid) {
-            m = moments_ct<CT>(c, p, ux, uy, F);
-        } else {
-            m = Mom<CT>{CT(0), CT(0), CT(0), CT(0), CT(0)};
-            ux = uy = F = CT(0);
-        }
-        UX[slot3(y)][k] = (float)ux;
-        UY[slot3(y)][k] = (float)uy;
-    };
-    auto put_mu = [&](int y) {
-        const int yw = wrap_small(y, g.ny);
+    // stencils of phi (rows s5m, s50, s5p), Gamma mu and the direction-free part of g^eq
+    auto mu_row = [&](int sl, int s5m, int s50, int s5p, bool fluid, unsigned sm, float& dx, float& dy,
+                      float& lap, float& gmu) {
         float v = 0.f;
-        if (!g.solid(col, yw)) {
-            float dx, dy, lap;
-            stencil3(PH[slot5(y - 1)], PH[slot5(y)], PH[slot5(y + 1)], k + 1, hood_of(g, col, yw).solid, G2, dx,
-                     dy, lap);
-            v = Gam * (mu_bulk(c, PH[slot5(y)][k + 1]) - kap * lap);
+        dx = dy = lap = gmu = 0.f;
+        if (fluid) {
+            stencil3(PH[s5m], PH[s50], PH[s5p], k + 1, sm, G2, dx, dy, lap);
+            const float ph = PH[s50][k + 1];
+            gmu = Gam * (mu_bulk(c, ph) - kap * lap);
+            const float ux = UX[sl][k], uy = UY[sl][k];
+            v = gmu - 0.5f * ph * (ux * ux + uy * uy);
         }
-        MU[slot3(y)][k] = v;
+        AM[sl][k] = v;
     };
 
-    // ---- prologue: rows ya-2 .. ya+1 of phi, u and mu of rows ya-1 and ya
-    {
-        float m0, e0;
-        for (int y = s.ya - 2; y <= s.ya + 1; ++y) {
-            load_phi_row(y, m0, e0);
-            store_phi_row(y, m0, e0);
-        }
-    }
-    Pulled pa;
-    Mom<CT> mom_cur, mom_tmp;
-    CT ux_cur, uy_cur, F_cur, tx, ty, tf;
-    pull_row(s.ya - 1, pa);
-    put_u(s.ya - 1, pa, mom_tmp, tx, ty, tf);
-    pull_row(s.ya, pa);
-    put_u(s.ya, pa, mom_cur, ux_cur, uy_cur, F_cur);
-    unsigned solid_cur = pa.solid;
-    bool fluid_cur = pa.fluid;
-    __syncthreads();
-    put_mu(s.ya - 1);
-    put_mu(s.ya);
-    // loads for the first iteration: pulled row ya+1, phi row ya+2
-    Pulled pnext;
-    float phn_m, phn_e;
-    pull_row(s.ya + 1, pnext);
-    load_phi_row(s.ya + 2, phn_m, phn_e);
+    // ring slots: row y+d of the phi ring is (p5 + 2 + d) mod 5, of the u/mu ring (p3 + 1 + d) mod 3
+    int p5 = 0, p3 = 0;   // slots of rows ya-2 and ya-1
+    auto r5 = [&](int d) { int v = p5 + 2 + d; v -= v >= 5 ? 5 : 0; v -= v >= 5 ? 5 : 0; return v; };
+    auto r3 = [&](int d) { int v = p3 + 1 + d; v -= v >= 3 ? 3 : 0; v -= v >= 3 ? 3 : 0; return v; };
 
-    for (int y = s.ya; y < s.yb; ++y) {
-        // (a) request the next iteration's data
-        Pulled ppre;
-        float php_m = 0.f, php_e = 0.f;
-        const bool more = y + 1 < s.yb;
-        if (more) {
-            pull_row(y + 2, ppre);
-            load_phi_row(y + 3, php_m, php_e);
-        }
-        // (b) row y+1: u, moments; phi row y+2
-        store_phi_row(y + 2, phn_m, phn_e);
-        Mom<CT> mom_next;
-        CT ux_n, uy_n, F_n;
-        put_u(y + 1, pnext, mom_next, ux_n, uy_n, F_n);
-        const unsigned solid_next = pnext.solid;
-        const bool fluid_next = pnext.fluid;
-        __syncthreads();
-        // (c) mu of row y+1
-        put_mu(y + 1);
-        __syncthreads();
-        // (d) row y: collision and phi update
-        const int yw = wrap_small(y, g.ny);
-        if (out_col && fluid_cur) {
-            const float* rm = PH[slot5(y - 1)];
-            const float* r0 = PH[slot5(y)];
-            const float* rp = PH[slot5(y + 1)];
-            float dxf, dyf, lapf;
-            stencil3(rm, r0, rp, k + 1, solid_cur, G2, dxf, dyf, lapf);
-            const float phi = r0[k + 1];
-            Mom<CT> m = mom_cur;
-            if (INIT) {
-                m.pxx = (CT)kap * ((CT)dxf * (CT)dxf - (CT)dyf * (CT)dyf);
-                m.pxy = (CT)kap * (CT)dxf * (CT)dyf;
-            }
+    // ---- prologue: phi rows ya-2..ya+1; u, mu of rows ya-1, ya
+    for (int d = -2; d <= 1; ++d) {
+        float m, e;
+        const RowInfo rr = row_info(g, s.ya + d);
+        phi_load(rr, m, e);
+        phi_store(r5(d), rr, m, e);
+    }
+    float f[9];
+    Mom<float> mom_cur;
+    RowInfo ri = row_info(g, s.ya - 1);
+    unsigned sm = solid_bits(L, ri);
+    bool fl = !(L.t0 && ri.w0);
+    pull_lane(fs, P, g.pitch, L, ri, sm, f);
+    u_row(r3(-1), f, fl, sm, mom_cur);
+    ri = row_info(g, s.ya);
+    unsigned sm_cur = solid_bits(L, ri);
+    bool fl_cur = !(L.t0 && ri.w0);
+    pull_lane(fs, P, g.pitch, L, ri, sm_cur, f);
+    u_row(r3(0), f, fl_cur, sm_cur, mom_cur);
+    wave_sync();
+    float dx_cur, dy_cur, lap_cur, gmu_cur, t0, t1, t2, t3;
+    mu_row(r3(-1), r5(-2), r5(-1), r5(0), fl, sm, t0, t1, t2, t3);
+    mu_row(r3(0), r5(-1), r5(0), r5(1), fl_cur, sm_cur, dx_cur, dy_cur, lap_cur, gmu_cur);
+    // Requests run one row ahead of the arithmetic.  The two request buffers swap
+    // roles every row (the loop is unrolled by two), so a finished request is
+    // never copied: a copy would wait for every load in flight.
+    struct Ahead {
+        float f[9];       // pulled populations of row y+1
+        float pm, pe;     // phi of row y+2 (own column, extra column)
+        RowInfo rph;      // row y+2
+        unsigned sm;
+        bool fl;
+    };
+    Ahead A, B;
+    {
+        const RowInfo rn = row_info(g, s.ya + 1);
+        A.sm = solid_bits(L, rn);
+        A.fl = !(L.t0 && rn.w0);
+        pull_lane(fs, P, g.pitch, L, rn, A.sm, A.f);
+        A.rph = row_info(g, s.ya + 2);
+        phi_load(A.rph, A.pm, A.pe);
+    }
+
+    // one row y: n holds the requests for row y+1, p receives those for row y+2
+    auto iter = [&](int y, Ahead& n, Ahead& p) {
+        // (a) requests for the next row: row y+2 pulled, phi row y+3.  In the last
+        // row of the chunk they repeat the previous requests (cache hits, unused):
+        // loads under a branch would make every later wait a wait for all loads.
+        const int ya2 = y + 1 < s.yb ? y + 2 : y + 1;
+        const RowInfo ri_p = row_info(g, ya2);
+        p.sm = solid_bits(L, ri_p);
+        p.fl = !(L.t0 && ri_p.w0);
+        p.rph = row_info(g, ya2 + 1);
+        pull_lane(fs, P, g.pitch, L, ri_p, p.sm, p.f);
+        phi_load(p.rph, p.pm, p.pe);
+        // keep the uses of the previous requests below the new ones
+        __builtin_amdgcn_sched_barrier(0);
+        // (b) phi row y+2; u and moments of row y+1
+        phi_store(r5(2), n.rph, n.pm, n.pe);
+        Mom<float> mom_n;
+        u_row(r3(1), n.f, n.fl, n.sm, mom_n);
+        wave_sync();
+        // (c) stencils and mu of row y+1
+        float dx_n, dy_n, lap_n, gmu_n;
+        mu_row(r3(1), r5(0), r5(1), r5(2), n.fl, n.sm, dx_n, dy_n, lap_n, gmu_n);
+        wave_sync();
+        // (d) collision and phi update of row y
+        if (out_col && fl_cur) {
+            const float phi = PH[r5(0)][k + 1];
+            const Mom<CT> mc{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
+            const CT F_cur = sm_cur ? CT(0) : (CT)c.Fx;
+            const CT rho_c = (CT)c.rho_ref + mc.drho;
+            const CT ux_cur = (mc.jx + CT(0.5) * F_cur) / rho_c, uy_cur = mc.jy / rho_c;
             const CT ph = (CT)phi, phib = (CT)c.phib;
-            const CT dX = m.drho * (CT(1) / CT(3)) +
+            const CT dX = mc.drho * (CT(1) / CT(3)) +
                           CT(0.25) * (CT)c.B * ((ph - phib) * (ph + phib)) * (CT(3) * ph * ph + phib * phib) -
-                          (CT)kap * ph * (CT)lapf;
+                          (CT)kap * ph * (CT)lap_cur;
             const CT pc = ph < CT(-1) ? CT(-1) : (ph > CT(1) ? CT(1) : ph);
             const CT nu = (CT)c.nu_g + CT(0.5) * (pc + CT(1)) * ((CT)c.nu_l - (CT)c.nu_g);
             const CT omega = CT(2) / (CT(6) * nu + CT(1));
             CT o[9];
-            collide(c, m, (CT)c.rho_ref + m.drho, ux_cur, uy_cur, dX, CT(0), omega, (CT)dxf, (CT)dyf, F_cur, o);
-            const long long idx = (long long)yw * g.pitch + col;
+            collide<CT, ST>(c, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            const int idx = row_info(g, y).y0 * g.pitch + L.c0;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fd[(long long)i * P + idx] = (float)o[i];
-            // phi(t+1) = phi(t) + sum_i [g^eq_i(source) - g^eq_i(r)]
-            const float uxf = (float)ux_cur, uyf = (float)uy_cur;
-            const float gmu = MU[slot3(y)][k];
-            float go[9];
-#pragma unroll
-            for (int i = 1; i < 9; ++i) go[i] = geq_i(i, phi, uxf, uyf, gmu);
-            float delta = 0.f;
+            for (int i = 0; i < 9; ++i) fd[i * P + idx] = (float)o[i];
+            // phi(t+1) = phi(t) + sum_i g^eq_i(source of i) - sum_i g^eq_i(r), i >= 1,
+            // where sum_i g^eq_i(r) = 5/3 Gamma mu + 2/3 phi |u|^2 (Appendix A moments)
+            const float uxf = UX[r3(0)][k], uyf = UY[r3(0)][k];
+            const float am = AM[r3(0)][k];
+            auto gq = [&](int i, float pp, float ax, float ay, float a0) {
+                const float eu = (float)ex_(i) * ax + (float)ey_(i) * ay;
+                return (i <= 4 ? 1.f / 3.f : 1.f / 12.f) * (a0 + pp * eu * (1.f + 1.5f * eu));
+            };
+            float gin_sum = 0.f;
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
                 float gin;
-                if ((solid_cur >> opp_(i)) & 1u) {
-                    gin = go[opp_(i)];
+                if ((sm_cur >> opp_(i)) & 1u) {
+                    gin = gq(opp_(i), phi, uxf, uyf, am);   // bounce-back of g*_opp(i)(r)
                 } else {
-                    const int sy = y - ey_(i), sk = k - ex_(i);
-                    gin = geq_i(i, PH[slot5(sy)][sk + 1], UX[slot3(sy)][sk], UY[slot3(sy)][sk], MU[slot3(sy)][sk]);
+                    const int s3 = r3(-ey_(i)), s5 = r5(-ey_(i)), sk = k - ex_(i);
+                    gin = gq(i, PH[s5][sk + 1], UX[s3][sk], UY[s3][sk], AM[s3][sk]);
                 }
-                delta += gin - go[i];
+                gin_sum += gin;
             }
-            pd[idx] = phi + delta;
+            const float gout_sum = (5.f / 3.f) * am + 1.5f * phi * (uxf * uxf + uyf * uyf);
+            pd[idx] = phi + (gin_sum - gout_sum);
         }
-        // (e) rotate
-        mom_cur = mom_next;
-        ux_cur = ux_n;
-        uy_cur = uy_n;
-        F_cur = F_n;
-        solid_cur = solid_next;
-        fluid_cur = fluid_next;
-        if (more) {
-            pnext = ppre;
-            phn_m = php_m;
-            phn_e = php_e;
-        }
-        __syncthreads();
+        // (e) rotate the row state
+        mom_cur = mom_n;
+        sm_cur = n.sm;
+        fl_cur = n.fl;
+        dx_cur = dx_n;
+        dy_cur = dy_n;
+        lap_cur = lap_n;
+        gmu_cur = gmu_n;
+        p5 = p5 == 4 ? 0 : p5 + 1;
+        p3 = p3 == 2 ? 0 : p3 + 1;
+        wave_sync();
+    };
+    for (int y = s.ya; y < s.yb; y += 2) {
+        iter(y, A, B);
+        if (y + 1 >= s.yb) break;
+        iter(y + 1, B, A);
     }
 }
 
 // ---- van der Waals model ---------------------------------------------------------
-template <bool INIT, typename CT>
+template <typename CT>
 __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
     const int si = strip_index(a);
     if (si >= a.nstrips) return;
     const StripDev s = a.strips[si];
-    const CapDev& c = a.caps[s.cap];
+    // by value: one scalar load at entry, kept in registers (a reference would be
+    // re-read from memory after every global store of the loop)
+    const CapDev c = a.caps[s.cap];
     const Geo g = geo_of(c);
-    const long long P = c.plane;
+    const int P = (int)c.plane;
     const int sb = a.cur ^ c.par;
-    const float* __restrict__ src = sb ? a.arena1 : a.arena0;
-    float* __restrict__ dst = sb ? a.arena0 : a.arena1;
-    const float* __restrict__ fs = src + c.off_f;
-    float* __restrict__ fd = dst + c.off_f;
+    const float* __restrict__ fs = (sb ? a.arena1 : a.arena0) + c.off_f;
+    float* __restrict__ fd = (sb ? a.arena0 : a.arena1) + c.off_f;
 
     __shared__ float Q[3][SW];         // drho rows, column xs-1+k at lane k
     const int k = threadIdx.x;
     const int xl = s.xs + k - 1;
-    const int col = wrap_small(xl, g.nx);
+    const LaneCols L = lane_cols(g, xl);
     const bool out_col = k >= 1 && k <= STRIP_OUT && xl < g.nx;
     const float G2 = 2.f * c.G;
-    auto slot3 = [&](int y) { return (y - s.ya + 9) % 3; };
-    // request a row: pulled populations (or, at initialisation, the initial field in f[0])
-    auto request = [&](int y, Pulled& p) {
-        const int yw = wrap_small(y, g.ny);
-        if (INIT) {
-            p.fluid = !g.solid(col, yw);
-            p.solid = hood_of(g, col, yw).solid;
-#pragma unroll
-            for (int i = 1; i < 9; ++i) p.f[i] = 0.f;
-            p.f[0] = p.fluid ? fs[(long long)yw * g.pitch + col] - c.rho_ref : 0.f;
-        } else {
-            pull_node(fs, P, g, col, yw, p);
-        }
-    };
-    // drho of a requested row (for INIT, f[0] holds it)
-    auto drho_of = [&](const Pulled& p) -> float { return p.fluid ? sum9(p.f) : 0.f; };
+    int p3 = 0;   // slot of row ya-1
+    auto r3 = [&](int d) { int v = p3 + 1 + d; v -= v >= 3 ? 3 : 0; v -= v >= 3 ? 3 : 0; return v; };
 
-    Pulled pc0, pn;
-    {
-        Pulled t;
-        request(s.ya - 1, t);
-        Q[slot3(s.ya - 1)][k] = drho_of(t);
-    }
-    request(s.ya, pc0);
-    Q[slot3(s.ya)][k] = drho_of(pc0);
-    request(s.ya + 1, pn);
-    for (int y = s.ya; y < s.yb; ++y) {
-        Pulled pp;
-        const bool more = y + 1 < s.yb;
-        if (more) request(y + 2, pp);
-        Q[slot3(y + 1)][k] = drho_of(pn);
-        __syncthreads();
-        const int yw = wrap_small(y, g.ny);
-        if (out_col && pc0.fluid) {
-            const float* rm = Q[slot3(y - 1)];
-            const float* r0 = Q[slot3(y)];
-            const float* rp = Q[slot3(y + 1)];
+    // three population buffers rotate (current row, row y+1, request for row y+2);
+    // the loop is unrolled by three so that no finished request is copied (a copy
+    // waits for every load in flight)
+    float fa[9], fb[9], fc[9];
+    RowInfo ri = row_info(g, s.ya - 1);
+    bool fl = !(L.t0 && ri.w0);
+    pull_lane(fs, P, g.pitch, L, ri, solid_bits(L, ri), fa);
+    Q[r3(-1)][k] = fl ? sum9(fa) : 0.f;
+    ri = row_info(g, s.ya);
+    unsigned sm_cur = solid_bits(L, ri);
+    bool fl_cur = !(L.t0 && ri.w0);
+    pull_lane(fs, P, g.pitch, L, ri, sm_cur, fa);
+    Q[r3(0)][k] = fl_cur ? sum9(fa) : 0.f;
+    RowInfo ri_n = row_info(g, s.ya + 1);
+    unsigned sm_n = solid_bits(L, ri_n);
+    bool fl_n = !(L.t0 && ri_n.w0);
+    pull_lane(fs, P, g.pitch, L, ri_n, sm_n, fb);
+
+    auto iter = [&](int y, const float (&f)[9], const float (&fn)[9], float (&fp)[9]) {
+        // request for row y+2; in the last row of the chunk it repeats the previous
+        // one (cache hits, unused): a load under a branch would make every later
+        // wait a wait for all loads
+        const RowInfo ri_p = row_info(g, y + 1 < s.yb ? y + 2 : y + 1);
+        const unsigned sm_p = solid_bits(L, ri_p);
+        const bool fl_p = !(L.t0 && ri_p.w0);
+        pull_lane(fs, P, g.pitch, L, ri_p, sm_p, fp);
+        // keep the uses of the previous requests below the new ones
+        __builtin_amdgcn_sched_barrier(0);
+        Q[r3(1)][k] = fl_n ? sum9(fn) : 0.f;
+        wave_sync();
+        if (out_col && fl_cur) {
             float dxf, dyf, lapf;
-            stencil3(rm, r0, rp, k, pc0.solid, G2, dxf, dyf, lapf);
-            const bool bnd = pc0.solid != 0u;
+            stencil3(Q[r3(-1)], Q[r3(0)], Q[r3(1)], k, sm_cur, G2, dxf, dyf, lapf);
+            const bool bnd = sm_cur != 0u;
             const CT F = bnd ? CT(0) : (CT)c.Fx;
-            Mom<CT> m;
-            if (INIT) {
-                m.drho = (CT)r0[k];
-                m.jx = m.jy = CT(0);
-                m.pxx = (CT)c.kappa * ((CT)dxf * (CT)dxf - (CT)dyf * (CT)dyf);
-                m.pxy = (CT)c.kappa * (CT)dxf * (CT)dyf;
-            } else {
-                CT f[9];
+            CT fcur[9];
 #pragma unroll
-                for (int i = 0; i < 9; ++i) f[i] = (CT)pc0.f[i];
-                m = moments_of(f, bnd);
-            }
+            for (int i = 0; i < 9; ++i) fcur[i] = (CT)f[i];
+            const Mom<CT> m = moments_of(fcur, bnd);
             const CT rho_ref = (CT)c.rho_ref;
             const CT rho = rho_ref + m.drho;
             const CT inv_rho = CT(1) / rho;
@@ -395,13 +441,23 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
             }
             CT o[9];
             collide(c, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
-            const long long idx = (long long)yw * g.pitch + col;
+            const int idx = row_info(g, y).y0 * g.pitch + L.c0;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fd[(long long)i * P + idx] = (float)o[i];
+            for (int i = 0; i < 9; ++i) fd[i * P + idx] = (float)o[i];
         }
-        pc0 = pn;
-        if (more) pn = pp;
-        __syncthreads();
+        sm_cur = sm_n;
+        fl_cur = fl_n;
+        sm_n = sm_p;
+        fl_n = fl_p;
+        p3 = p3 == 2 ? 0 : p3 + 1;
+        wave_sync();
+    };
+    for (int y = s.ya; y < s.yb; y += 3) {
+        iter(y, fa, fb, fc);
+        if (y + 1 >= s.yb) break;
+        iter(y + 1, fb, fc, fa);
+        if (y + 2 >= s.yb) break;
+        iter(y + 2, fc, fa, fb);
     }
 }
 

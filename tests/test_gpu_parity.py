@@ -277,12 +277,16 @@ def test_autotune_keeps_state(L):
     p = L.params_from_workload(w, wall_grad=oracle_wall_grad(w))
     g = L.geometry_from_workload(w)
     a = L.Lattice(p, g, w.initial_field())
+    cfg0 = a.launch_config()
     a.step(40)
     cfg, us = a.autotune(trial_steps=6)
     assert cfg.schedule in (0, 1, 2, 3) and us > 0
     assert a.t == 40
     a.step(60)
+    # a new lattice of this size class starts from the tuned shape: replay a's history
     b = L.Lattice(p, g, w.initial_field())
+    assert b.launch_config().asdict() == cfg.asdict()
+    b.set_launch_config(**cfg0.asdict())
     b.step(40)
     b.set_launch_config(**cfg.asdict())
     b.step(60)
