@@ -21,3 +21,4 @@ from .oracle import (  # noqa: F401
     geq,
     collide,
 )
+from . import mlp_oracle  # noqa: F401,E402

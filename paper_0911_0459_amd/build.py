@@ -10,8 +10,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbcap.so")
 
-SOURCES = ["lb_api.hip", "lb_thermo.cpp"]
-HEADERS = ["lb_internal.h", "lb_kernels.h", "lb_thermo.h", "mlp_kernels.h"]
+SOURCES = ["lb_api.hip", "lb_thermo.cpp", "mlp.hip"]
+HEADERS = ["lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_thermo.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -742,6 +742,9 @@ __global__ void __launch_bounds__(256) lb_copy_kernel(const float4* __restrict__
 
 }  // namespace
 
+// error hook of the other translation units of the library
+lb_status lbk::set_error(lb_status s, const char* msg) { return fail(s, msg); }
+
 extern "C" {
 
 lb_status lb_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {

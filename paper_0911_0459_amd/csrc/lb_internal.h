@@ -4,7 +4,12 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lbcap.h"
+
 namespace lbk {
+
+// Records the message returned by lb_last_error and returns s.
+lb_status set_error(lb_status s, const char* msg);
 
 constexpr int TILE_W = 64;  // tile width along x = one wavefront
 

@@ -89,6 +89,14 @@ _SIGS = {
     "lb_autotune": (C.c_int, [_vp, C.c_int, C.POINTER(lb_launch_config), _dp]),
     "lb_last_step_kernel_us": (C.c_int, [_vp, _dp]),
     "lb_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "mlp_init": (C.c_int, [C.POINTER(_vp), C.c_int, _vp]),
+    "mlp_free": (None, [_vp]),
+    "mlp_param_count": (C.c_long, [_vp]),
+    "mlp_get_params": (C.c_int, [_vp, _fp, C.c_long]),
+    "mlp_set_params": (C.c_int, [_vp, _fp, C.c_long]),
+    "mlp_predict": (C.c_int, [_vp, _fp, C.c_int, _fp]),
+    "mlp_loss_grad": (C.c_int, [_vp, _fp, _fp, C.c_int, _fp, _fp]),
+    "mlp_train": (C.c_int, [_vp, _fp, _fp, C.c_int, C.c_int, C.c_int, C.c_float, C.c_int, _fp]),
 }
 
 EXPORTED = tuple(_SIGS)
