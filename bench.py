@@ -11,8 +11,11 @@ per second (MLUPS) with the populations resident in HBM before timing starts.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sweep|single4096|single1024]
 
 Prints one JSON line.  Adds the roofline of the step kernel (algorithmic bytes
-per fluid-node update x updates per launch / HIP-event launch time) and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+per fluid-node update x updates per launch / HIP-event launch time), the FP64
+CPU oracle timed on a bounded sample of the same workload, and (sweep
+workload) the wall time of the whole 100000-step sweep three ways: plain
+sequential runs, one batched run, and the batched run with learned early
+stopping, with the true error of every accepted tail.
 """
 from __future__ import annotations
 
@@ -31,14 +34,18 @@ BYTES_PER_LUP = {"vdw": 72, "binary": 80}   # read + write of every stored FP32 
 
 
 def kernel_source_hash() -> str:
-    path = os.path.join(ROOT, "paper_0911_0459_amd", "csrc", "lb_kernels.h")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    """Hash of the sources of the step kernels (the counter summary in
+    profiles/ is only used while it matches)."""
+    h = hashlib.sha256()
+    for name in ("lb_internal.h", "lb_kernels.h", "lb_strip.h"):
+        h.update(open(os.path.join(ROOT, "paper_0911_0459_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str):
+def traffic_from_profiles(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None if absent or taken on another version of the kernel source."""
-    path = os.path.join(ROOT, "profiles", f"lb_step_kernel_{workload}_counters.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
     if not os.path.exists(path):
         return None
     try:
@@ -108,6 +115,46 @@ def cpu_baseline(w, target_s: float = 15.0):
                       f"{n} steps, {dt:.1f} s"}
 
 
+def sweep_compare(works, log):
+    """Wall time of the 256-capillary sweep: plain sequential runs (estimated
+    from 1000 timed steps of each), one batched run, and the batched run with
+    learned early stopping; the true error of every accepted tail is taken
+    from the full batched run."""
+    import numpy as np
+    from paper_0911_0459_amd import surrogate as S
+    net_path = os.path.join(S.DATA_DIR, "surrogate_net.npz")
+    if not os.path.exists(net_path):
+        return None
+    T = works[0].steps
+    full = S.run_sweep(works, T, None, log=log)
+    sur = S.Surrogate.load(net_path)
+    early = S.run_sweep(works, T, sur, log=log)
+    plain = S.plain_sequential_estimate(works, T, log=log)
+    hist = np.stack(full["hist"])
+    p = S.RunParams.of(works)
+    truth = S.interp_history(hist, T, S.out_times(T))
+    acc = early["accept"]
+    err = (np.abs(early["pred"] - truth) / truth).max(axis=1)
+    wb = S.washburn_predict(p, hist[:, :S.N_EARLY], T)
+    ev_wb = S.evaluate(p, wb, hist, T)
+    acc_wb = ev_wb["accept"]
+    return {
+        "capillaries": len(works), "steps_per_run": T,
+        "plain_sequential_s": round(plain["estimated_s"], 1),
+        "plain_sequential_note": f"estimated from {plain['sample_steps']} timed steps of each run",
+        "batched_s": round(full["wall_s"], 1),
+        "batched_surrogate_s": round(early["wall_s"], 1),
+        "speedup_batched_surrogate_vs_plain": round(plain["estimated_s"] / early["wall_s"], 2),
+        "speedup_batched_surrogate_vs_batched": round(full["wall_s"] / early["wall_s"], 2),
+        "accepted": int(acc.sum()),
+        "accepted_true_err_max": round(float(err[acc].max()), 5) if acc.any() else None,
+        "accepted_over_1pct": int(np.sum(acc & (err > 0.01))),
+        "washburn_gate": {"accepted": int(acc_wb.sum()),
+                          "accepted_over_1pct": int(np.sum(acc_wb & (ev_wb["true_err"] > 0.01)))},
+        "unstable": int(np.sum(full["health"] != 0)),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +167,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=-1)
     ap.add_argument("--fp64-arith", type=int, default=-1)
     ap.add_argument("--chunk-rows", type=int, default=-1)
+    ap.add_argument("--graph-steps", type=int, default=-1, help="steps per HIP graph (0: direct launches)")
     ap.add_argument("--copy-probe", action="store_true", help="time the plain copy kernel only")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the sweep wall-time comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -145,9 +194,9 @@ def main():
     if not args.no_autotune:
         cfg, _ = lat.autotune(trial_steps=10)
     cfg = lat.launch_config()
-    if args.tile_rows or args.schedule >= 0 or args.fp64_arith >= 0 or args.chunk_rows >= 0:
+    if args.tile_rows or args.schedule >= 0 or args.fp64_arith >= 0 or args.chunk_rows >= 0 or args.graph_steps >= 0:
         lat.set_launch_config(args.tile_rows or cfg.tile_rows, cfg.schedule if args.schedule < 0 else args.schedule,
-                              cfg.persist_blocks_per_cu, cfg.graph_steps,
+                              cfg.persist_blocks_per_cu, cfg.graph_steps if args.graph_steps < 0 else args.graph_steps,
                               cfg.fp64_arith if args.fp64_arith < 0 else args.fp64_arith,
                               cfg.chunk_rows if args.chunk_rows < 0 else args.chunk_rows)
         cfg = lat.launch_config()
@@ -167,7 +216,9 @@ def main():
     mlups = fluid * args.steps / elapsed / 1e6
     bpl = BYTES_PER_LUP[model]
     achieved = bpl * fluid / (us_kernel * 1e-6) / 1e9 if us_kernel > 0 else None
-    traffic = traffic_from_profiles(args.workload)
+    kname = (f"lb_strip_{'bin' if model == 'binary' else 'vdw'}" if cfg.schedule == 3
+             else f"lb_step_kernel_{model}_{cfg.tile_rows}")
+    traffic = traffic_from_profiles(kname, args.workload)
     config.update({"model": model, "fluid_nodes": fluid, "launch": cfg.asdict(), "bytes_per_lup": bpl})
     out = {
         "metric": "MLUPS (fluid-node updates/s) and fraction of HBM roofline",
@@ -185,8 +236,7 @@ def main():
         "config": config,
         "roofline": {
             "bound": "hbm",
-            "kernel": (f"lb_strip_{'bin' if model == 'binary' else 'vdw'}" if cfg.schedule == 3
-                       else f"lb_step_kernel<{1 if model == 'binary' else 0},{cfg.tile_rows}>"),
+            "kernel": kname,
             "achieved": round(achieved, 1) if achieved else None,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -198,6 +248,10 @@ def main():
         "cpu_baseline": None,
     }
     lat.close()
+    del lat
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.workload == "sweep" and not args.no_sweep:
+        out["sweep"] = sweep_compare(works, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(works[0])
     print(json.dumps(out))

@@ -12,6 +12,7 @@
  - conservation of mass and of the order parameter.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -25,11 +26,26 @@ VDW = dict(model="vdw", kappa=0.02, a=9 / 49, b=2 / 21, T=0.56)
 BIN = dict(model="binary", kappa=0.04, A=0.04, B=0.04, Gamma=1.0)
 
 
+def _printed():
+    """Values printed in the paper (tests/golden/paper_values.txt, with citations)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            name, value, tol = line.split()[:3]
+            out[name] = (float(value), None if tol == "-" else float(tol))
+    return out
+
+
 def test_continuum_references():
+    g = _printed()
     rl, rg = P.vdw_maxwell()
-    assert abs(rl - 4.54) / 4.54 < 0.01 and abs(rg - 2.59) / 2.59 < 0.02     # printed, Sec. 2
-    assert abs(P.vdw_tension() - 0.0112) / 0.0112 < 0.01                      # printed, Sec. 2
-    assert abs(P.vdw_contact_angle(-0.144) - 60.0) < 0.6                      # printed, Sec. 2.2
+    (pl, tl), (pg, tg) = g["vdw_rho_liquid"], g["vdw_rho_gas"]
+    assert abs(rl - pl) / pl < tl and abs(rg - pg) / pg < tg
+    pt, tt = g["vdw_tension"]
+    assert abs(P.vdw_tension() - pt) / pt < tt
+    pa, ta = g["vdw_contact_angle"]
+    assert abs(P.vdw_contact_angle(g["vdw_wall_gradient"][0]) - pa) < ta
     assert abs(P.binary_tension() - 2 * math.sqrt(2) / 3 * 0.04) < 1e-10      # phi^4 closed form
     assert P.binary_contact_angle(0.0) == 90.0
 
