@@ -224,6 +224,8 @@ lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L
         c.active = 1;
         c.par = 0;
         c.plane = (long long)g.ny * c.pitch;
+        // the kernels address one capillary's planes with 32-bit byte offsets
+        if (10 * 4 * c.plane > 0x7fffffffLL) return fail(LB_EINVAL, "lattice too large: one capillary's state must stay below 2 GiB");
         c.off_f = off;
         c.off_phi = off + 9 * c.plane;
         off += (p.model == LB_BINARY ? 10 : 9) * c.plane;

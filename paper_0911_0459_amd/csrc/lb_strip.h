@@ -92,6 +92,7 @@ __device__ __forceinline__ int strip_index(const StripArgs& a) {
 // two neighbours (periodic), and whether each lies in the tube section.
 struct LaneCols {
     int c0, cm, cp;
+    int b0, bm, bp;       // the same columns as byte offsets within a row
     bool t0, tm, tp;
 };
 
@@ -100,6 +101,9 @@ __device__ __forceinline__ LaneCols lane_cols(const Geo& g, int xl) {
     L.c0 = wrap_mod(xl, g.nx);
     L.cm = L.c0 == 0 ? g.nx - 1 : L.c0 - 1;
     L.cp = L.c0 == g.nx - 1 ? 0 : L.c0 + 1;
+    L.b0 = 4 * L.c0;
+    L.bm = 4 * L.cm;
+    L.bp = 4 * L.cp;
     L.t0 = g.tube_col(L.c0);
     L.tm = g.tube_col(L.cm);
     L.tp = g.tube_col(L.cp);
@@ -132,26 +136,62 @@ __device__ __forceinline__ unsigned solid_bits(const LaneCols& L, const RowInfo&
            ((unsigned)(L.tm && r.wp) << 7) | ((unsigned)(L.tp && r.wm) << 8);
 }
 
+// One capillary's planes of an arena seen through a buffer resource.  Accesses
+// take a 32-bit per-lane byte offset (the column) and a scalar byte offset (the
+// plane and the row), so no per-lane 64-bit address arithmetic is spent on
+// them; the hardware checks every access against the region's size.
+constexpr int RAW_BUFFER_WORD3 = 0x00020000;   // descriptor dword 3: raw 32-bit data, no swizzle
+
+struct Planes {
+    __amdgpu_buffer_rsrc_t rs;
+    int pb;                       // bytes per plane
+    int rb;                       // bytes per row
+};
+
+__device__ __forceinline__ Planes planes_of(const float* base, int nplanes, int P, int pitch) {
+    Planes q;
+    q.rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, nplanes * P * 4, RAW_BUFFER_WORD3);
+    q.pb = 4 * P;
+    q.rb = 4 * pitch;
+    return q;
+}
+
+// (the b32 builtins move raw 32-bit words: the float is reinterpreted, not converted)
+__device__ __forceinline__ float ld(const Planes& q, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(q.rs, voff, soff, 0));
+}
+
+__device__ __forceinline__ void st(const Planes& q, float v, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), q.rs, voff, soff, 0);
+}
+
 // Pull of the lane's node on a row (bounce-back for solid sources).  Straight-line
 // code, the source chosen by selects: a branch around the loads (even a uniform
 // one) makes the compiler's wait counting assume the path without them, so
 // that every later use of an older load would wait for these ones as well.
-__device__ __forceinline__ void pull_lane(const float* __restrict__ fs, int P, int pitch, const LaneCols& L,
-                                          const RowInfo& r, unsigned sm, float (&f)[9]) {
-    const int o0 = r.y0 * pitch, om = r.ym * pitch, op = r.yp * pitch;
-    const int own = o0 + L.c0;
-    auto src = [&](int i, int off) -> int {
-        return ((sm >> opp_(i)) & 1u) ? opp_(i) * P + own : i * P + off;
+// For each direction the scalar offset is the smaller of the two candidate
+// sources (streaming: plane i, the source row; bounce-back: plane opp(i), the
+// node's own row), so the per-lane offset of either choice is non-negative.
+__device__ __forceinline__ void pull_lane(const Planes& q, const LaneCols& L, const RowInfo& r, unsigned sm,
+                                          float (&f)[9]) {
+    const int s0 = r.y0 * q.rb, sm_ = r.ym * q.rb, sp = r.yp * q.rb;
+    auto get = [&](int i, int col, int srow) -> float {
+        const bool bb = (sm >> opp_(i)) & 1u;
+        if (i & 1) {   // opp(i) = i + 1: the streaming source has the smaller offset
+            return ld(q, bb ? L.b0 + q.pb + (s0 - srow) : col, i * q.pb + srow);
+        } else {       // opp(i) = i - 1: the bounce-back source has the smaller offset
+            return ld(q, bb ? L.b0 : col + q.pb + (srow - s0), (i - 1) * q.pb + s0);
+        }
     };
-    f[0] = fs[own];
-    f[1] = fs[src(1, o0 + L.cm)];
-    f[2] = fs[src(2, o0 + L.cp)];
-    f[3] = fs[src(3, om + L.c0)];
-    f[4] = fs[src(4, op + L.c0)];
-    f[5] = fs[src(5, om + L.cm)];
-    f[6] = fs[src(6, op + L.cp)];
-    f[7] = fs[src(7, om + L.cp)];
-    f[8] = fs[src(8, op + L.cm)];
+    f[0] = ld(q, L.b0, s0);
+    f[1] = get(1, L.bm, s0);
+    f[2] = get(2, L.bp, s0);
+    f[3] = get(3, L.b0, sm_);
+    f[4] = get(4, L.b0, sp);
+    f[5] = get(5, L.bm, sm_);
+    f[6] = get(6, L.bp, sp);
+    f[7] = get(7, L.bp, sm_);
+    f[8] = get(8, L.bm, sp);
 }
 
 // ---- binary model --------------------------------------------------------------
@@ -167,10 +207,10 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
     const Geo g = geo_of(c);
     const int P = (int)c.plane;
     const int sb = a.cur ^ c.par;
-    const float* __restrict__ fs = (sb ? a.arena1 : a.arena0) + c.off_f;
-    const float* __restrict__ ps = (sb ? a.arena1 : a.arena0) + c.off_phi;
-    float* __restrict__ fd = (sb ? a.arena0 : a.arena1) + c.off_f;
-    float* __restrict__ pd = (sb ? a.arena0 : a.arena1) + c.off_phi;
+    const Planes fs = planes_of((sb ? a.arena1 : a.arena0) + c.off_f, 9, P, c.pitch);
+    const Planes ps = planes_of((sb ? a.arena1 : a.arena0) + c.off_phi, 1, P, c.pitch);
+    const Planes fd = planes_of((sb ? a.arena0 : a.arena1) + c.off_f, 9, P, c.pitch);
+    const Planes pd = planes_of((sb ? a.arena0 : a.arena1) + c.off_phi, 1, P, c.pitch);
 
     __shared__ float PH[5][PHW];                         // phi rows, column xs-2+j at index j
     // column xs-1+k at lane k: velocity and Gamma mu - phi |u|^2 / 2, the part of g^eq
@@ -189,10 +229,10 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
 
     // phi loads are issued unconditionally (solid nodes have valid addresses) and
     // masked when stored, so that no instruction waits on them early
-    const int cx = k < 2 ? ce : L.c0;
+    const int bx = 4 * (k < 2 ? ce : L.c0);
     auto phi_load = [&](const RowInfo& r, float& m, float& e) {
-        m = ps[r.y0 * g.pitch + L.c0];
-        e = ps[r.y0 * g.pitch + cx];
+        m = ld(ps, L.b0, r.y0 * ps.rb);
+        e = ld(ps, bx, r.y0 * ps.rb);
     };
     auto phi_store = [&](int sl, const RowInfo& r, float m, float e) {
         PH[sl][k + 1] = (L.t0 && r.w0) ? 0.f : m;
@@ -247,12 +287,12 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
     RowInfo ri = row_info(g, s.ya - 1);
     unsigned sm = solid_bits(L, ri);
     bool fl = !(L.t0 && ri.w0);
-    pull_lane(fs, P, g.pitch, L, ri, sm, f);
+    pull_lane(fs, L, ri, sm, f);
     u_row(r3(-1), f, fl, sm, mom_cur);
     ri = row_info(g, s.ya);
     unsigned sm_cur = solid_bits(L, ri);
     bool fl_cur = !(L.t0 && ri.w0);
-    pull_lane(fs, P, g.pitch, L, ri, sm_cur, f);
+    pull_lane(fs, L, ri, sm_cur, f);
     u_row(r3(0), f, fl_cur, sm_cur, mom_cur);
     wave_sync();
     float dx_cur, dy_cur, lap_cur, gmu_cur, t0, t1, t2, t3;
@@ -273,7 +313,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
         const RowInfo rn = row_info(g, s.ya + 1);
         A.sm = solid_bits(L, rn);
         A.fl = !(L.t0 && rn.w0);
-        pull_lane(fs, P, g.pitch, L, rn, A.sm, A.f);
+        pull_lane(fs, L, rn, A.sm, A.f);
         A.rph = row_info(g, s.ya + 2);
         phi_load(A.rph, A.pm, A.pe);
     }
@@ -288,7 +328,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
         p.sm = solid_bits(L, ri_p);
         p.fl = !(L.t0 && ri_p.w0);
         p.rph = row_info(g, ya2 + 1);
-        pull_lane(fs, P, g.pitch, L, ri_p, p.sm, p.f);
+        pull_lane(fs, L, ri_p, p.sm, p.f);
         phi_load(p.rph, p.pm, p.pe);
         // keep the uses of the previous requests below the new ones
         __builtin_amdgcn_sched_barrier(0);
@@ -307,19 +347,23 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
             const Mom<CT> mc{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
             const CT F_cur = sm_cur ? CT(0) : (CT)c.Fx;
             const CT rho_c = (CT)c.rho_ref + mc.drho;
-            const CT ux_cur = (mc.jx + CT(0.5) * F_cur) / rho_c, uy_cur = mc.jy / rho_c;
+            const CT inv_rho = CT(1) / rho_c;
+            const CT ux_cur = (mc.jx + CT(0.5) * F_cur) * inv_rho, uy_cur = mc.jy * inv_rho;
             const CT ph = (CT)phi, phib = (CT)c.phib;
             const CT dX = mc.drho * (CT(1) / CT(3)) +
                           CT(0.25) * (CT)c.B * ((ph - phib) * (ph + phib)) * (CT(3) * ph * ph + phib * phib) -
                           (CT)kap * ph * (CT)lap_cur;
-            const CT pc = ph < CT(-1) ? CT(-1) : (ph > CT(1) ? CT(1) : ph);
-            const CT nu = (CT)c.nu_g + CT(0.5) * (pc + CT(1)) * ((CT)c.nu_l - (CT)c.nu_g);
-            const CT omega = CT(2) / (CT(6) * nu + CT(1));
+            // the relaxation rate only scales the shear stresses (FP32) and the
+            // forcing term, so it is formed in FP32 with the hardware reciprocal
+            // (1 ulp)
+            const float pc = phi < -1.f ? -1.f : (phi > 1.f ? 1.f : phi);
+            const float nu = c.nu_g + 0.5f * (pc + 1.f) * (c.nu_l - c.nu_g);
+            const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
             CT o[9];
             collide<CT, ST>(c, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
-            const int idx = row_info(g, y).y0 * g.pitch + L.c0;
+            const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fd[i * P + idx] = (float)o[i];
+            for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
             // phi(t+1) = phi(t) + sum_i g^eq_i(source of i) - sum_i g^eq_i(r), i >= 1,
             // where sum_i g^eq_i(r) = 5/3 Gamma mu + 2/3 phi |u|^2 (Appendix A moments)
             const float uxf = UX[r3(0)][k], uyf = UY[r3(0)][k];
@@ -341,7 +385,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
                 gin_sum += gin;
             }
             const float gout_sum = (5.f / 3.f) * am + 1.5f * phi * (uxf * uxf + uyf * uyf);
-            pd[idx] = phi + (gin_sum - gout_sum);
+            st(pd, phi + (gin_sum - gout_sum), L.b0, srow);
         }
         // (e) rotate the row state
         mom_cur = mom_n;
@@ -374,8 +418,8 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
     const Geo g = geo_of(c);
     const int P = (int)c.plane;
     const int sb = a.cur ^ c.par;
-    const float* __restrict__ fs = (sb ? a.arena1 : a.arena0) + c.off_f;
-    float* __restrict__ fd = (sb ? a.arena0 : a.arena1) + c.off_f;
+    const Planes fs = planes_of((sb ? a.arena1 : a.arena0) + c.off_f, 9, P, c.pitch);
+    const Planes fd = planes_of((sb ? a.arena0 : a.arena1) + c.off_f, 9, P, c.pitch);
 
     __shared__ float Q[3][SW];         // drho rows, column xs-1+k at lane k
     const int k = threadIdx.x;
@@ -392,17 +436,17 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
     float fa[9], fb[9], fc[9];
     RowInfo ri = row_info(g, s.ya - 1);
     bool fl = !(L.t0 && ri.w0);
-    pull_lane(fs, P, g.pitch, L, ri, solid_bits(L, ri), fa);
+    pull_lane(fs, L, ri, solid_bits(L, ri), fa);
     Q[r3(-1)][k] = fl ? sum9(fa) : 0.f;
     ri = row_info(g, s.ya);
     unsigned sm_cur = solid_bits(L, ri);
     bool fl_cur = !(L.t0 && ri.w0);
-    pull_lane(fs, P, g.pitch, L, ri, sm_cur, fa);
+    pull_lane(fs, L, ri, sm_cur, fa);
     Q[r3(0)][k] = fl_cur ? sum9(fa) : 0.f;
     RowInfo ri_n = row_info(g, s.ya + 1);
     unsigned sm_n = solid_bits(L, ri_n);
     bool fl_n = !(L.t0 && ri_n.w0);
-    pull_lane(fs, P, g.pitch, L, ri_n, sm_n, fb);
+    pull_lane(fs, L, ri_n, sm_n, fb);
 
     auto iter = [&](int y, const float (&f)[9], const float (&fn)[9], float (&fp)[9]) {
         // request for row y+2; in the last row of the chunk it repeats the previous
@@ -411,7 +455,7 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
         const RowInfo ri_p = row_info(g, y + 1 < s.yb ? y + 2 : y + 1);
         const unsigned sm_p = solid_bits(L, ri_p);
         const bool fl_p = !(L.t0 && ri_p.w0);
-        pull_lane(fs, P, g.pitch, L, ri_p, sm_p, fp);
+        pull_lane(fs, L, ri_p, sm_p, fp);
         // keep the uses of the previous requests below the new ones
         __builtin_amdgcn_sched_barrier(0);
         Q[r3(1)][k] = fl_n ? sum9(fn) : 0.f;
@@ -441,9 +485,9 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
             }
             CT o[9];
             collide(c, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
-            const int idx = row_info(g, y).y0 * g.pitch + L.c0;
+            const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fd[i * P + idx] = (float)o[i];
+            for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
         }
         sm_cur = sm_n;
         fl_cur = fl_n;
