@@ -159,10 +159,20 @@ int count_tiles(const lb_geometry& g, int rows) {
 // section only covers the channel rows.  chunk = 0 keeps whole strips.
 constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
 
+// Strip table of the row-sweep kernels.  Every strip column (62 output
+// columns of one capillary, over the rows that hold fluid) is cut into chunks:
+// chunk rows each, except (for chunks of 16 rows or more) the last 2 * small
+// rows, which are cut into chunks of small = max(4, chunk / 4) rows.  The columns are dealt to the 8 XCDs in
+// contiguous runs of about equal row count; each XCD's run lists the long
+// chunks of its columns first and the short ones last, so the end of a step is
+// made of short strips (a small tail) while most rows go through long strips
+// (few prologues), and the chunks of one column share an L2.
+// xcd_start[x] .. xcd_start[x + 1] is XCD x's run.
 void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk,
-                  std::vector<StripDev>* out, int* count) {
-    int n = 0;
-    if (out) out->clear();
+                  std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
+    struct Col { int cap, xs, ya, yb; };
+    std::vector<Col> cols;
+    long long rows = 0;
     for (size_t k = 0; k < G.size(); ++k) {
         if (!active[k]) continue;
         const lb_geometry& g = G[k];
@@ -171,13 +181,42 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
             const bool in_tube = g.tube_len > 0 && xs >= g.x_in && xe <= g.x_in + g.tube_len;
             const int ya = in_tube ? g.y0 : 0;
             const int yb = in_tube ? g.y0 + g.tube_h : g.ny;
-            const int step = chunk > 0 ? chunk : (yb - ya);
-            for (int y = ya; y < yb; y += step) {
-                if (out) out->push_back(StripDev{(int)k, xs, y, std::min(y + step, yb)});
+            cols.push_back(Col{(int)k, xs, ya, yb});
+            rows += yb - ya;
+        }
+    }
+    // (chunks below 16 rows are short enough to end a step without a tail)
+    const int small = chunk < 16 ? chunk : std::max(LB_MIN_CHUNK, chunk / 4);
+    int n = 0;
+    if (out) out->clear();
+    std::vector<StripDev> tails;
+    size_t ci = 0;
+    long long done = 0;
+    for (int x = 0; x < 8; ++x) {
+        if (xcd_start) xcd_start[x] = n;
+        const long long goal = rows * (x + 1) / 8;
+        tails.clear();
+        for (; ci < cols.size() && (done < goal || x == 7); ++ci) {
+            const Col& c = cols[ci];
+            done += c.yb - c.ya;
+            if (chunk <= 0) {
+                if (out) out->push_back(StripDev{c.cap, c.xs, c.ya, c.yb});
+                ++n;
+                continue;
+            }
+            const int tail = chunk < 16 ? 0 : std::min(c.yb - c.ya, 2 * small);
+            for (int y = c.ya; y < c.yb - tail; y += chunk) {
+                if (out) out->push_back(StripDev{c.cap, c.xs, y, std::min(y + chunk, c.yb - tail)});
+                ++n;
+            }
+            for (int y = c.yb - tail; y < c.yb; y += small) {
+                tails.push_back(StripDev{c.cap, c.xs, y, std::min(y + small, c.yb)});
                 ++n;
             }
         }
+        if (out) out->insert(out->end(), tails.begin(), tails.end());
     }
+    if (xcd_start) xcd_start[8] = n;
     if (count) *count = n;
 }
 
@@ -344,6 +383,7 @@ struct lb_ctx {
     int ntiles = 0;
     StripDev* d_strips = nullptr;
     int nstrips = 0;
+    int xcd_start[9] = {};    // strip runs of the 8 XCDs
     float* d_lnow = nullptr;
     float* d_hist = nullptr;
     long long* d_hist_t = nullptr;
@@ -382,7 +422,7 @@ lb_status upload_tiles(lb_ctx* c) {
         HIP_TRY(hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(), hipMemcpyHostToDevice,
                                c->stream));
     std::vector<StripDev> strips;
-    build_strips(c->G, c->active, c->cfg.chunk_rows, &strips, nullptr);
+    build_strips(c->G, c->active, c->cfg.chunk_rows, &strips, nullptr, c->xcd_start);
     if ((int)strips.size() > c->L.max_strips) return fail(LB_EINVAL, "strip table overflow");
     c->nstrips = (int)strips.size();
     if (!strips.empty())
@@ -440,11 +480,16 @@ void enqueue_step(lb_ctx* c, bool init) {
         a.caps = c->d_caps;
         a.strips = c->d_strips;
         a.nstrips = c->nstrips;
-        a.xcd_group = 1;
+        int longest = 0;
+        for (int x = 0; x < 8; ++x) {
+            a.xcd_start[x] = c->xcd_start[x];
+            longest = std::max(longest, c->xcd_start[x + 1] - c->xcd_start[x]);
+        }
+        a.xcd_start[8] = c->xcd_start[8];
         a.arena0 = c->arena[0];
         a.arena1 = c->arena[1];
         a.cur = c->cur;
-        const int grid = 8 * ((c->nstrips + 7) / 8);
+        const int grid = 8 * longest;
         if (c->model == LB_VDW) {
             if (c->cfg.fp64_arith)
                 launch_strip_t<0, double, double>(c, a, grid);
@@ -1057,7 +1102,7 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     const lb_launch_config orig = c->cfg;
     std::vector<lb_launch_config> cand;
     const int ar = orig.fp64_arith;   // the arithmetic is a choice of the caller, not tuned
-    for (int ch : {6, 8, 12, 16, 0}) cand.push_back({orig.tile_rows, 3, 4, 0, ar, ch});
+    for (int ch : {6, 8, 12, 16, 32}) cand.push_back({orig.tile_rows, 3, 4, 0, ar, ch});
     for (int r : {4, 8}) {
         cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
         cand.push_back({r, 2, 4, 0, ar, orig.chunk_rows});

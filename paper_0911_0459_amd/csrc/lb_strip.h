@@ -36,7 +36,7 @@ struct StripArgs {
     const CapDev* caps;
     const StripDev* strips;
     int nstrips;
-    int xcd_group;                // 1: each XCD takes a contiguous run of strips
+    int xcd_start[9];             // XCD x works through strips xcd_start[x] .. xcd_start[x + 1] - 1
     float* arena0;
     float* arena1;
     int cur;
@@ -82,10 +82,12 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin: workgroup b runs on XCD b % 8
+// as that XCD's (b / 8)-th; -1 past the end of the XCD's run.
 __device__ __forceinline__ int strip_index(const StripArgs& a) {
-    if (!a.xcd_group) return blockIdx.x;
-    const int per = (a.nstrips + 7) >> 3;
-    return (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int x = blockIdx.x & 7;
+    const int i = a.xcd_start[x] + (int)(blockIdx.x >> 3);
+    return i < a.xcd_start[x + 1] ? i : -1;
 }
 
 // Column data of one lane, fixed for the whole strip: the lane's column and its
@@ -199,7 +201,7 @@ __device__ __forceinline__ void pull_lane(const Planes& q, const LaneCols& L, co
 template <typename MT, typename CT, typename ST = CT>
 __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
     const int si = strip_index(a);
-    if (si >= a.nstrips) return;
+    if (si < 0) return;
     const StripDev s = a.strips[si];
     // by value: one scalar load at entry, kept in registers (a reference would be
     // re-read from memory after every global store of the loop)
@@ -410,7 +412,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
 template <typename CT>
 __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
     const int si = strip_index(a);
-    if (si >= a.nstrips) return;
+    if (si < 0) return;
     const StripDev s = a.strips[si];
     // by value: one scalar load at entry, kept in registers (a reference would be
     // re-read from memory after every global store of the loop)
