@@ -366,28 +366,35 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
-            // phi(t+1) = phi(t) + sum_i g^eq_i(source of i) - sum_i g^eq_i(r), i >= 1,
-            // where sum_i g^eq_i(r) = 5/3 Gamma mu + 2/3 phi |u|^2 (Appendix A moments)
+            // phi(t+1) = phi(t) + sum_i g^eq_i(source of i) - sum_i g^eq_i(r), i >= 1.
+            // With g^eq_i = w_i (A + phi e_i.u (1 + 3/2 e_i.u)), A = Gamma mu - phi |u|^2 / 2,
+            // sum_i w_i = 5/3 and sum_i w_i (e_i.u)^2 = |u|^2 (Appendix A moments), this is
+            //   sum_i w_i [(A_src - A) + phi_src e_i.u_src (1 + 3/2 e_i.u_src)] - 3/2 phi |u|^2.
+            // Writing the A part as differences makes the update of a uniform region
+            // exactly zero; a closed-form sum_i w_i A would not round like the eight
+            // incoming terms, and the same small excess at every bulk node would
+            // drift the total phi steadily.
             const float uxf = UX[r3(0)][k], uyf = UY[r3(0)][k];
             const float am = AM[r3(0)][k];
-            auto gq = [&](int i, float pp, float ax, float ay, float a0) {
+            auto adv = [&](int i, float pp, float ax, float ay) {
                 const float eu = (float)ex_(i) * ax + (float)ey_(i) * ay;
-                return (i <= 4 ? 1.f / 3.f : 1.f / 12.f) * (a0 + pp * eu * (1.f + 1.5f * eu));
+                return pp * eu * (1.f + 1.5f * eu);
             };
-            float gin_sum = 0.f;
+            float sa = 0.f, sd = 0.f;   // axis and diagonal sums
 #pragma unroll
             for (int i = 1; i < 9; ++i) {
-                float gin;
+                float t;
                 if ((sm_cur >> opp_(i)) & 1u) {
-                    gin = gq(opp_(i), phi, uxf, uyf, am);   // bounce-back of g*_opp(i)(r)
+                    t = adv(opp_(i), phi, uxf, uyf);   // bounce-back of g*_opp(i)(r): no A difference
                 } else {
                     const int s3 = r3(-ey_(i)), s5 = r5(-ey_(i)), sk = k - ex_(i);
-                    gin = gq(i, PH[s5][sk + 1], UX[s3][sk], UY[s3][sk], AM[s3][sk]);
+                    t = (AM[s3][sk] - am) + adv(i, PH[s5][sk + 1], UX[s3][sk], UY[s3][sk]);
                 }
-                gin_sum += gin;
+                if (i <= 4) sa += t;
+                else sd += t;
             }
-            const float gout_sum = (5.f / 3.f) * am + 1.5f * phi * (uxf * uxf + uyf * uyf);
-            st(pd, phi + (gin_sum - gout_sum), L.b0, srow);
+            const float dphi = (sa * (1.f / 3.f) + sd * (1.f / 12.f)) - 1.5f * phi * (uxf * uxf + uyf * uyf);
+            st(pd, phi + dphi, L.b0, srow);
         }
         // (e) rotate the row state
         mom_cur = mom_n;
