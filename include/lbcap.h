@@ -140,6 +140,25 @@ lb_status lb_moments_device(lb_ctx* c, float* rho, float* ux, float* uy, float* 
  * Synchronises.  LB_EINVAL if the geometry has no tube. */
 lb_status lb_interface_length(lb_ctx* c, double* l, double* l_eff);
 
+/* Contact angle of the meniscus in the tube (Sec. 3.2, Fig. 5): in every tube
+ * row except edge_rows rows next to each wall, the interface is the first
+ * position from the inlet where q (phi, or rho for vdW) falls below q_mid,
+ * linearly interpolated (rows with no liquid at the inlet are skipped).  A
+ * circle centred on the channel centreline is fitted to these points by linear
+ * least squares; with the walls half a node outside the boundary rows the
+ * channel is H wide and cos(theta) = (H/2)/R, positive when the centre lies on
+ * the gas side.  theta_deg is measured through the liquid (liquid on the inlet
+ * side), radius is R (INFINITY for a flat interface), apex_x the interface
+ * position on the centreline; each output pointer may be NULL.
+ * lb_meniscus_angle_field works on a caller-owned host field q (ny x nx,
+ * row-major) and needs no device; lb_meniscus_angle reads capillary cap of a
+ * context (synchronises).  LB_EINVAL: no tube, edge_rows leaves fewer than 3
+ * rows; LB_ESTATE: fewer than 3 rows hold an interface. */
+lb_status lb_meniscus_angle_field(const double* q, const lb_geometry* g, double q_mid, int edge_rows,
+                                  double* theta_deg, double* radius, double* apex_x);
+lb_status lb_meniscus_angle(lb_ctx* c, int cap, int edge_rows, double* theta_deg, double* radius,
+                            double* apex_x);
+
 /* Wall gradient that gives the equilibrium contact angle theta_deg by Young's
  * law (Eq. Young) with the surface tensions of the Cahn construction for a
  * surface energy linear in the wall value of rho/phi (Sec. 2.2, Fig. 2).

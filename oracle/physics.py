@@ -207,6 +207,32 @@ def drop_contact_angle(field, level, y_wall, mask=None, y_min_fit=None):
     return math.degrees(math.acos(max(-1.0, min(1.0, c)))), (xc, yc, R)
 
 
+def meniscus_angle(q, x_in, tube_len, y0, tube_h, q_mid, edge_rows=2):
+    """Contact angle (degrees, through the liquid, liquid on the inlet side) of
+    the meniscus in a channel of width tube_h (walls half a node outside the
+    boundary rows), as analysed for the dynamic angles of Sec. 3.2: interface
+    crossings of q_mid scanned from the inlet in the rows away from the walls,
+    an unconstrained algebraic circle fit, and cos(theta) = (tube_h / 2) / R with
+    the sign of the side (gas: +, liquid: -) on which the centre lies."""
+    xs, ys = [], []
+    for y in range(y0 + edge_rows, y0 + tube_h - edge_rows):
+        row = q[y]
+        if row[x_in] < q_mid:
+            continue
+        for k in range(1, tube_len):
+            a, b = row[x_in + k - 1], row[x_in + k]
+            if b < q_mid:
+                xs.append(x_in + k - 1 + (a - q_mid) / (a - b))
+                ys.append(float(y))
+                break
+    xs, ys = np.array(xs), np.array(ys)
+    xc, yc, R = fit_circle(xs, ys)
+    apex = xs[np.argmin(np.abs(ys - (y0 + 0.5 * (tube_h - 1))))]
+    sign = 1.0 if xc > apex else -1.0
+    c = sign * min(1.0, 0.5 * tube_h / R)
+    return math.degrees(math.acos(c)), R
+
+
 def linear_fit(x, y):
     """Least-squares line and its coefficient of determination."""
     x, y = np.asarray(x, float), np.asarray(y, float)

@@ -922,6 +922,18 @@ lb_status lb_interface_length(lb_ctx* c, double* l, double* l_eff) {
     return LB_OK;
 }
 
+lb_status lb_meniscus_angle(lb_ctx* c, int cap, int edge_rows, double* theta_deg, double* radius, double* apex_x) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (lb_status s = cap_index(c, cap)) return s;
+    const lb_geometry& g = c->G[cap];
+    if (g.tube_len <= 0) return fail(LB_EINVAL, "no tube in this geometry");
+    const size_t n = (size_t)g.nx * g.ny;
+    std::vector<double> rho(n), ux(n), uy(n), phi(n);
+    if (lb_status s = host_moments(c, cap, rho.data(), ux.data(), uy.data(), phi.data())) return s;
+    const double* q = c->model == LB_BINARY ? phi.data() : rho.data();
+    return lb_meniscus_angle_field(q, &g, (double)c->L.caps[cap].q_mid, edge_rows, theta_deg, radius, apex_x);
+}
+
 lb_status lb_batch_l_history(lb_ctx* c, int cap, double* l, long* steps, int max_samples, int* n_samples) {
     if (lb_status s = check_ctx(c)) return s;
     if (lb_status s = cap_index(c, cap)) return s;

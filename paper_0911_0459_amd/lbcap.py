@@ -89,6 +89,8 @@ _SIGS = {
     "lb_autotune": (C.c_int, [_vp, C.c_int, C.POINTER(lb_launch_config), _dp]),
     "lb_last_step_kernel_us": (C.c_int, [_vp, _dp]),
     "lb_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
+    "lb_meniscus_angle_field": (C.c_int, [_dp, C.POINTER(lb_geometry), C.c_double, C.c_int, _dp, _dp, _dp]),
+    "lb_meniscus_angle": (C.c_int, [_vp, C.c_int, C.c_int, _dp, _dp, _dp]),
     "mlp_init": (C.c_int, [C.POINTER(_vp), C.c_int, _vp]),
     "mlp_free": (None, [_vp]),
     "mlp_param_count": (C.c_long, [_vp]),
@@ -172,6 +174,17 @@ def lb_stream_copy(dst, src, stream=None):
     assert dst.numel() * dst.element_size() == nbytes
     s = torch.cuda.current_stream().cuda_stream if stream is None else stream
     _check(_lib.lb_stream_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, C.c_void_p(s)))
+
+
+def lb_meniscus_angle_field(q: np.ndarray, g: lb_geometry, q_mid: float, edge_rows: int = 2):
+    """(theta_deg, radius, apex_x) of the meniscus in a host field q (ny x nx)."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    if q.size != g.nx * g.ny:
+        raise LbError(LB_EINVAL, "field size does not match the geometry")
+    th, R, ax = C.c_double(), C.c_double(), C.c_double()
+    _check(_lib.lb_meniscus_angle_field(_d(q), C.byref(g), float(q_mid), int(edge_rows), C.byref(th),
+                                        C.byref(R), C.byref(ax)))
+    return th.value, R.value, ax.value
 
 
 def lb_state_bytes(p: lb_params, g: lb_geometry) -> int:
@@ -280,6 +293,12 @@ class Lattice:
                                        C.byref(n)))
         m = min(n.value, LB_HISTORY_CAP)
         return steps[:m].copy(), buf[:m].copy()
+
+    def meniscus_angle(self, cap: int = 0, edge_rows: int = 2):
+        """(theta_deg, radius, apex_x) of capillary cap's meniscus."""
+        th, R, ax = C.c_double(), C.c_double(), C.c_double()
+        _check(_lib.lb_meniscus_angle(self._h, cap, int(edge_rows), C.byref(th), C.byref(R), C.byref(ax)))
+        return th.value, R.value, ax.value
 
     def retire(self, cap: int):
         _check(_lib.lb_batch_retire(self._h, cap))
