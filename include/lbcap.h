@@ -259,7 +259,7 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
 lb_status lb_last_step_kernel_us(lb_ctx* c, double* us);
 
 /* Device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned
- * pointers) by a plain grid-stride kernel with 16-byte loads and stores,
+ * pointers) by a plain kernel with one 16-byte load and store per thread,
  * enqueued on hip_stream.  Measurement infrastructure, not part of the
  * method: it is the achievable-bandwidth reference for the step kernel's
  * roofline and the kernel of known traffic that calibrates the HBM byte

@@ -778,13 +778,13 @@ lb_status set_active(lb_ctx* c, int k, int on) {
     return upload_tiles(c);
 }
 
-// Plain grid-stride copy with 16-byte accesses: the achievable-bandwidth
-// reference of the step kernel's roofline and the calibration kernel of the
-// HBM byte counters.
+// Plain copy, one 16-byte element per thread (the fastest of the simple copy
+// shapes on this GPU): the achievable-bandwidth reference of the step kernel's
+// roofline and the calibration kernel of the HBM byte counters.
 __global__ void __launch_bounds__(256) lb_copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
                                                       size_t n4) {
-    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < n4) dst[i] = src[i];
 }
 
 }  // namespace
@@ -799,7 +799,8 @@ lb_status lb_stream_copy(void* dst, const void* src, size_t bytes, void* hip_str
         return fail(LB_EINVAL, "copy needs 16-byte aligned pointers and a multiple of 16 bytes");
     const size_t n4 = bytes / 16;
     if (n4 == 0) return LB_OK;
-    const int grid = (int)std::min<size_t>((n4 + 255) / 256, 256 * 32);
+    if ((n4 + 255) / 256 > 0x7fffffffull) return fail(LB_EINVAL, "copy too large");
+    const unsigned grid = (unsigned)((n4 + 255) / 256);
     hipLaunchKernelGGL(lb_copy_kernel, dim3(grid), dim3(256), 0, (hipStream_t)hip_stream, (const float4*)src,
                        (float4*)dst, n4);
     HIP_TRY(hipGetLastError());
