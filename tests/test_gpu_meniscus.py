@@ -155,3 +155,40 @@ def test_mobility_parity_with_oracle(L, gamma):
     drho, dphi, du = field_errors(w, lat.moments(), orc)
     lat.close()
     assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6
+
+
+def test_liquid_gas_filling_is_driven_by_condensation(L):
+    """The paper's liquid-gas capillary (Sec. 2.2, Fig. 3 and Fig. 10): 700 x 40
+    fluid rows, x-periodic, a wetting tube of length 350 (walls at -0.144,
+    60 degrees) between y-periodic reservoirs, nu = 1/6, started with l = 10.
+    After 50000 steps the gas ahead of the meniscus flows back towards it, the
+    meniscus advances faster than the liquid behind it flows (the difference
+    condenses at the interface), and the filled length exceeds Washburn's law
+    (Eq. 3) and its version with gas drag."""
+    g = I.Geometry(nx=700, ny=42, x_in=175, tube_len=350, tube_h=40, y0=1)
+    w = I.Workload("vdw_700x40", "vdw", g, 0, 0, 7, nu_l=1 / 6, nu_g=1 / 6, theta_deg=60.0, wall_grad=-0.144,
+                   liquid=4.54, gas=2.59, **I.VDW_CONSTS)
+    q = w.initial_field()
+    q[g.y0:g.y0 + g.tube_h, g.x_in:g.x_in + 10] = 4.54
+    lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), q)
+    lat.step(45_000)
+    l0 = lat.interface_length()[0]
+    lat.step(5_000)
+    l1 = lat.interface_length()[0]
+    rho, ux, uy, _ = lat.moments()
+    lat.close()
+    x_m = g.x_in + int(l1)
+    rows = slice(g.y0, g.y0 + g.tube_h)
+    gas_ahead = ux[g.y0 + g.tube_h // 2, x_m + 3:x_m + 40].mean()
+    liquid_flux = (rho[rows, g.x_in + 5:x_m - 3] * ux[rows, g.x_in + 5:x_m - 3]).sum(axis=0).mean()
+    liquid_mass = rho[rows, g.x_in + 5:x_m - 3].sum(axis=0).mean()
+    u_liquid = liquid_flux / liquid_mass               # mean liquid velocity over the cross-section
+    v_meniscus = (l1 - l0) / 5_000.0
+    assert gas_ahead < 0.0 < u_liquid
+    assert v_meniscus > 1.5 * u_liquid
+    # Washburn (Eq. 3) from l = 10: l^2 = 100 + H gamma cos(theta) t / (3 eta_l), eta_l = rho_l nu
+    from oracle import physics as P
+    rl, rg = P.vdw_maxwell()
+    gamma, t = P.vdw_tension(), 50_000.0
+    l_w = math.sqrt(100.0 + g.tube_h * gamma * 0.5 * t / (3.0 * rl / 6.0))
+    assert l1 > 1.2 * l_w
