@@ -53,7 +53,7 @@ def field_errors(w: I.Workload, gpu, orc):
     fluid = ~w.geom.solid()
     rho, ux, uy, phi = gpu
     r_o, ux_o, uy_o, phi_o = orc
-    drho = float((np.abs(rho - r_o) / np.abs(r_o))[fluid].max())
+    drho = float((np.abs(rho - r_o)[fluid] / np.abs(r_o)[fluid]).max())
     dphi = float(np.abs(phi - phi_o)[fluid].max())
     du = float(max(np.abs(ux - ux_o)[fluid].max(), np.abs(uy - uy_o)[fluid].max()))
     return drho, dphi, du
