@@ -172,8 +172,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep wall-time comparison")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(capillaries are independent; see DESIGN.md for how the sweep would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the capillaries of a sweep are independent and would be dealt to ranks by fluid-node count)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

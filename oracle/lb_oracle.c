@@ -16,7 +16,9 @@
  *  - e5 = (1,1), e6 = (-1,-1), e7 = (-1,1), e8 = (1,-1), which makes the jx and jy
  *    rows of the Appendix A matrix the momentum components;
  *  - lambda (Eq. equilibrium, value not given): vdW (1/omega - 1/2)(1/3 - dp0/drho),
- *    binary 0; lambda_mode = 1 switches it off;
+ *    binary 0; lambda_mode = 1 switches it off.  Parity unpinned: the paper
+ *    gives no value to check it against (it vanishes at equilibrium, so the
+ *    coexistence, Laplace and Young pins do not see it);
  *  - binary f^eq: the Eq. (equilibrium) form with X = p0 - kappa phi lap(phi) and the
  *    kappa terms in the gradients of phi, so that its second moment is the binary
  *    pressure tensor of Sec. 3.1 plus rho u u;

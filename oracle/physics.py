@@ -10,6 +10,9 @@ lattice code; they are the independent side of the pins:
   - least-squares fits used to read lattice results: circle through an
     interface contour (Sec. 3.2), straight lines for Washburn's law (Eq. 3),
     a parabola for Poiseuille flow (Eq. 1).
+The binary interface tension here is the continuum (phi^4) value; the value
+the paper prints for it (Sec. 3.1) is not reproduced by it or by the lattice:
+parity with that printed number is unpinned.
 """
 from __future__ import annotations
 

@@ -19,7 +19,7 @@ import torch  # noqa: F401
 from .build import LIB
 
 if not os.path.exists(LIB):
-    raise ImportError(f"liblbcap.so not found at {LIB}: run __graft_entry__.build() (hipcc, gfx950) first")
+    raise ImportError(f"liblbcap.so not found at {LIB}: build it first: python -m paper_0911_0459_amd.build (hipcc, gfx950)")
 
 _lib = C.CDLL(LIB)
 

@@ -25,7 +25,8 @@ the whole tail is at most SPREAD_TOL, the meniscus had entered the tube by
 the end of the early window, and the predicted liquid column stays well
 inside the reservoir's liquid; otherwise it continues to T.  Both limits
 are tighter than the 1 % accuracy asked of the accepted tails (ACCEPT_ERR).
-The lattice Boltzmann run is always the judge.
+The lattice Boltzmann run always has the final
+word.
 
 The comparison method without the network fits the same balance with both c
 and d free (least squares on the second half of the early window) and

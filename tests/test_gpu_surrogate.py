@@ -2,7 +2,7 @@
 sweep driver on the GPU.
 
 The held-out runs (master seeds 9000..9511, 100000 steps each, recorded by
-the library) are the judge: an accepted run's predicted tail must be within
+the library) are the reference: an accepted run's predicted tail must be within
 1 % of the recorded l_eff everywhere, and the network must accept more runs
 than the Washburn extrapolation without it, with fewer wrong acceptances.
 """
