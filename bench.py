@@ -8,7 +8,7 @@ HIP graphs, with the filled length of every capillary recorded every 625 steps.
 A step is one time step of all capillaries.  The metric is fluid-node updates
 per second (MLUPS) with the populations resident in HBM before timing starts.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sweep|single4096|single1024]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload sweep|single4096|single1024|vdw4096]
 
 Prints one JSON line.  Adds the roofline of the step kernel (algorithmic bytes
 per fluid-node update x updates per launch / HIP-event launch time), the FP64
@@ -66,6 +66,9 @@ def build_workload(name: str):
         w = I.binary_capillary_4096x256()
         return [w], {"workload": "binary_4096x256_ratio10_60deg", "lattice": "4096x256", "tube_h": 100,
                      "tube_len": 3072}
+    if name == "vdw4096":
+        w = I.vdw_capillary_4096x256()
+        return [w], {"workload": "vdw_4096x256_60deg", "lattice": "4096x256", "tube_h": 100, "tube_len": 3072}
     if name == "single1024":
         w = I.binary_capillary_1024x128()
         return [w], {"workload": "binary_1024x128_ratio10_60deg", "lattice": "1024x128", "tube_h": 40,
@@ -160,7 +163,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "single4096", "single1024"])
+    ap.add_argument("--workload", default="sweep", choices=["sweep", "single4096", "single1024", "vdw4096"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0, help="pin the launch shape (with --schedule)")

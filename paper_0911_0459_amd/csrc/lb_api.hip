@@ -1106,10 +1106,14 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     if (trial_steps < 2) return fail(LB_EINVAL, "trial_steps must be >= 2");
     // back up both arenas: the trials advance the lattices
     const size_t ab = sizeof(float) * (size_t)c->L.arena_floats;
-    float* backup = nullptr;
-    HIP_TRY(hipMalloc(&backup, 2 * ab));
-    HIP_TRY(hipMemcpyAsync(backup, c->arena[0], ab, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync((char*)backup + ab, c->arena[1], ab, hipMemcpyDeviceToDevice, c->stream));
+    float* raw = nullptr;
+    if (hipMalloc(&raw, 2 * ab) != hipSuccess) return fail(LB_ENOMEM, "no device memory for the autotune backup");
+    struct Backup {
+        float* p;
+        ~Backup() { (void)hipFree(p); }
+    } backup{raw};
+    HIP_TRY(hipMemcpyAsync(backup.p, c->arena[0], ab, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync((char*)backup.p + ab, c->arena[1], ab, hipMemcpyDeviceToDevice, c->stream));
     const long t0 = c->t;
     const int cur0 = c->cur;
     const lb_launch_config orig = c->cfg;
@@ -1123,16 +1127,22 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     double best_us = 1e300;
     lb_launch_config best_cfg = orig;
     lb_status st = LB_OK;
+    auto hip_ok = [&](hipError_t e, const char* what) {
+        if (e == hipSuccess) return true;
+        st = fail(LB_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+        return false;
+    };
     for (const auto& cf0 : cand) {
         lb_launch_config cf = cf0;
         if ((st = lb_set_launch_config(c, &cf))) break;
         if ((st = run_steps(c, 2))) break;  // warm-up
-        HIP_TRY(hipEventRecord(c->ev0, c->stream));
+        if (!hip_ok(hipEventRecord(c->ev0, c->stream), "hipEventRecord")) break;
         if ((st = run_steps(c, trial_steps))) break;
-        HIP_TRY(hipEventRecord(c->ev1, c->stream));
-        HIP_TRY(hipEventSynchronize(c->ev1));
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+        if (!hip_ok(hipEventRecord(c->ev1, c->stream), "hipEventRecord") ||
+            !hip_ok(hipEventSynchronize(c->ev1), "hipEventSynchronize") ||
+            !hip_ok(hipEventElapsedTime(&ms, c->ev0, c->ev1), "hipEventElapsedTime"))
+            break;
         const double us = 1000.0 * ms / trial_steps;
         if (us < best_us) {
             best_us = us;
@@ -1141,15 +1151,16 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     }
     // graphs reduce launch gaps: keep them for the winner
     best_cfg.graph_steps = 64;
-    // restore the state and time
-    HIP_TRY(hipMemcpyAsync(c->arena[0], backup, ab, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->arena[1], (char*)backup + ab, ab, hipMemcpyDeviceToDevice, c->stream));
+    // restore the state and time, also after a failed trial
+    HIP_TRY(hipMemcpyAsync(c->arena[0], backup.p, ab, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->arena[1], (char*)backup.p + ab, ab, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    HIP_TRY(hipFree(backup));
     c->cur = cur0;
     c->t = t0;
     if (st) {
+        const std::string msg = g_err;
         lb_set_launch_config(c, &orig);
+        g_err = msg;
         return st;
     }
     if ((st = lb_set_launch_config(c, &best_cfg))) return st;

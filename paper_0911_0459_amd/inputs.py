@@ -141,6 +141,15 @@ def vdw_capillary_256x64(seed: int = 1) -> Workload:
                     liquid=4.54, gas=2.59, **VDW_CONSTS)
 
 
+def vdw_capillary_4096x256(seed: int = 9) -> Workload:
+    """The liquid-gas model at the size of the binary throughput runs: 4096x256,
+    tube H=100 and length 3072, the C1 constants (nu = 0.1, -0.144)."""
+    g = Geometry(nx=4096, ny=256, x_in=1024, tube_len=3072, tube_h=100, y0=78)
+    return Workload("vdw_4096x256", "vdw", g, steps=200_000, sample_every=2000, seed=seed,
+                    nu_l=0.1, nu_g=0.1, theta_deg=60.0, wall_grad=-0.144,
+                    liquid=4.54, gas=2.59, **VDW_CONSTS)
+
+
 def binary_capillary_1024x128(seed: int = 2, ratio: float = 10.0) -> Workload:
     """Binary, 1024x128, tube H=40 and length 768, reservoir 256 wide,
     viscosity ratio 10, 60 degrees, 50k steps."""
