@@ -2,6 +2,8 @@
 oracle and through the GPU library, compare fields."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 from oracle import Oracle, OracleGeom, OracleParams
@@ -57,3 +59,15 @@ def field_errors(w: I.Workload, gpu, orc):
     dphi = float(np.abs(phi - phi_o)[fluid].max())
     du = float(max(np.abs(ux - ux_o)[fluid].max(), np.abs(uy - uy_o)[fluid].max()))
     return drho, dphi, du
+
+
+def printed_values():
+    """Values printed in the paper, with their tolerances, from
+    tests/golden/paper_values.txt (name -> (value, tolerance or None))."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.txt")
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            name, value, tol = line.split()[:3]
+            out[name] = (float(value), None if tol == "-" else float(tol))
+    return out

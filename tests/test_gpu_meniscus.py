@@ -192,3 +192,34 @@ def test_liquid_gas_filling_is_driven_by_condensation(L):
     gamma, t = P.vdw_tension(), 50_000.0
     l_w = math.sqrt(100.0 + g.tube_h * gamma * 0.5 * t / (3.0 * rl / 6.0))
     assert l1 > 1.2 * l_w
+
+
+def test_binary_capillary_of_the_paper(L):
+    """The binary capillary of Sec. 3.2 (Fig. 5) at the paper's geometry: 700 x 40
+    fluid rows, a wetting tube of length 350 at a static angle of 60 degrees,
+    equal viscosities 1/6, liquid filling the reservoir on the inlet side,
+    started at l = 10.  The filled length grows linearly in time (the paper's
+    circles; R^2 >= 0.999 over 40000 steps) and the meniscus angle settles
+    at a steady value above the static one, within 5 degrees of the 63 degrees
+    the paper reports (tests/golden/paper_values.txt)."""
+    g = I.Geometry(nx=700, ny=42, x_in=175, tube_len=350, tube_h=40, y0=1)
+    w = I.Workload("bin_700x40", "binary", g, 0, 0, 8, nu_l=1 / 6, nu_g=1 / 6, theta_deg=60.0, liquid=1.0,
+                   gas=-1.0, gas_frac=0.0, **I.BIN_CONSTS)
+    q = w.initial_field()
+    q[g.y0:g.y0 + g.tube_h, g.x_in:g.x_in + 10] = 1.0
+    lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), q)
+    ts, ls, th = [], [], []
+    for _ in range(10):
+        lat.step(4000)
+        ts.append(lat.t)
+        ls.append(lat.interface_length()[1])
+        th.append(lat.meniscus_angle()[0])
+    lat.close()
+    from oracle import physics as P
+    m, c, r2 = P.linear_fit(ts, ls)
+    assert m > 0 and r2 >= 0.999
+    late = np.array(th[5:])
+    assert late.max() - late.min() < 2.0
+    from tests.helpers import printed_values
+    printed = printed_values()["binary_dynamic_angle"][0]
+    assert 60.0 < late.mean() < printed + 5.0

@@ -73,6 +73,14 @@ def test_flat_interface_coexistence(model):
     else:
         assert abs(fld.max() - 1.0) < 1e-3 and abs(fld.min() + 1.0) < 1e-3
         gamma_cont = P.binary_tension()
+        # interface width: distance from phi = -0.9 to phi = +0.9 across the left interface
+        # (tanh profile of width sqrt(kappa/A): 2 sqrt(2) atanh(0.9) = 4.16; printed ~4)
+        left = fld[16:48]
+        xs = np.arange(16, 48, dtype=float)
+        x_lo = np.interp(-0.9, left, xs)
+        x_hi = np.interp(0.9, left, xs)
+        width, wtol = _printed()["binary_interface_width"]
+        assert abs((x_hi - x_lo) - width) / width < wtol
     # excess free energy of the lattice profile: sum kappa (d q/dx)^2 over both interfaces
     d = (np.roll(fld, -1) - np.roll(fld, 1)) / 2.0
     gamma_lat = p.kappa * (d * d).sum() / 2.0
