@@ -37,7 +37,7 @@ def kernel_source_hash() -> str:
     """Hash of the sources of the step kernels (the counter summary in
     profiles/ is only used while it matches)."""
     h = hashlib.sha256()
-    for name in ("lb_internal.h", "lb_kernels.h", "lb_strip.h"):
+    for name in ("lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_wide.h"):
         h.update(open(os.path.join(ROOT, "paper_0911_0459_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -220,8 +220,8 @@ def main():
     mlups = fluid * args.steps / elapsed / 1e6
     bpl = BYTES_PER_LUP[model]
     achieved = bpl * fluid / (us_kernel * 1e-6) / 1e9 if us_kernel > 0 else None
-    kname = (f"lb_strip_{'bin' if model == 'binary' else 'vdw'}" if cfg.schedule == 3
-             else f"lb_step_kernel_{model}_{cfg.tile_rows}")
+    kname = ({3: "lb_strip_", 4: "lb_wide_"}[cfg.schedule] + ("bin" if model == "binary" else "vdw")
+             if cfg.schedule in (3, 4) else f"lb_step_kernel_{model}_{cfg.tile_rows}")
     traffic = traffic_from_profiles(kname, args.workload)
     config.update({"model": model, "fluid_nodes": fluid, "launch": cfg.asdict(), "bytes_per_lup": bpl})
     out = {

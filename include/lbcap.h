@@ -222,17 +222,21 @@ int       lb_batch_size(const lb_ctx* c);
 long long lb_fluid_nodes(const lb_ctx* c);
 
 /* Launch configuration of the step kernel.
- *  schedule: 3 (default) row-sweep strips: one wavefront per strip of 62
+ *  schedule: 3 row-sweep strips: one wavefront per strip of 62
  *    output columns marching along y through chunks of chunk_rows rows (0: the
  *    whole height), strips grouped so that each of the 8 XCDs works on a
  *    contiguous run of them; every population row is read once per step.
+ *    4 (default) the same row sweep with a workgroup per strip of 192 output columns
+ *    aligned to the row pitch (three wavefronts of 64 output columns and one
+ *    that supplies the two neighbour columns), so that no stored cache line is
+ *    shared between workgroups; bitwise the same results as 3.
  *    0..2 tiles of 64 x tile_rows nodes with the order field recomputed on a
  *    halo: 0 one workgroup per tile in table order, 1 tiles grouped per XCD,
  *    2 persistent workgroups (persist_blocks_per_cu x 256 CUs) striding the table.
  *  tile_rows: rows per tile for schedules 0..2 (1, 2, 4 or 8).
- *  chunk_rows: rows per strip chunk for schedule 3 (0, or 4..4096; default 8).
+ *  chunk_rows: rows per strip chunk for schedules 3 and 4 (0, or 4..4096; default 8).
  *  graph_steps: steps captured per HIP graph (even, >= 2; 0 = no graphs).
- *  fp64_arith: 1 evaluates the collision in FP64 (schedule 3; schedules 0..2
+ *  fp64_arith: 1 evaluates the collision in FP64 (schedules 3, 4; schedules 0..2
  *    then compute the whole step in FP64), 0 in FP32.  The stored state is FP32
  *    either way (same memory traffic). */
 typedef struct {

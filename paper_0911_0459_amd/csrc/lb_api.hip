@@ -25,6 +25,7 @@
 #include "lb_internal.h"
 #include "lb_kernels.h"
 #include "lb_strip.h"
+#include "lb_wide.h"
 #include "lb_thermo.h"
 
 using namespace lbk;
@@ -159,7 +160,7 @@ int count_tiles(const lb_geometry& g, int rows) {
 // section only covers the channel rows.  chunk = 0 keeps whole strips.
 constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
 
-// Strip table of the row-sweep kernels.  Every strip column (62 output
+// Strip table of the row-sweep kernels.  Every strip column (width output
 // columns of one capillary, over the rows that hold fluid) is cut into chunks:
 // chunk rows each, except (for chunks of 16 rows or more) the last 2 * small
 // rows, which are cut into chunks of small = max(4, chunk / 4) rows.  The columns are dealt to the 8 XCDs in
@@ -168,7 +169,7 @@ constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
 // made of short strips (a small tail) while most rows go through long strips
 // (few prologues), and the chunks of one column share an L2.
 // xcd_start[x] .. xcd_start[x + 1] is XCD x's run.
-void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk,
+void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk, int width,
                   std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
     struct Col { int cap, xs, ya, yb; };
     std::vector<Col> cols;
@@ -176,8 +177,8 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
     for (size_t k = 0; k < G.size(); ++k) {
         if (!active[k]) continue;
         const lb_geometry& g = G[k];
-        for (int xs = 0; xs < g.nx; xs += STRIP_OUT) {
-            const int xe = std::min(xs + STRIP_OUT, g.nx);
+        for (int xs = 0; xs < g.nx; xs += width) {
+            const int xe = std::min(xs + width, g.nx);
             const bool in_tube = g.tube_len > 0 && xs >= g.x_in && xe <= g.x_in + g.tube_len;
             const int ya = in_tube ? g.y0 : 0;
             const int yb = in_tube ? g.y0 + g.tube_h : g.ny;
@@ -318,7 +319,11 @@ lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L
     {
         std::vector<lb_geometry> gv(G, G + n);
         std::vector<int> all(n, 1);
-        build_strips(gv, all, LB_MIN_CHUNK, nullptr, &L.max_strips);   // the finest chunking allowed
+        // the finest chunking allowed, for either strip width
+        int narrow = 0, wide = 0;
+        build_strips(gv, all, LB_MIN_CHUNK, STRIP_OUT, nullptr, &narrow);
+        build_strips(gv, all, LB_MIN_CHUNK, WIDE_OUT, nullptr, &wide);
+        L.max_strips = std::max(narrow, wide);
     }
     size_t o = 0;
     L.off_caps = o;
@@ -394,7 +399,7 @@ struct lb_ctx {
     bool own_stream = false;
     int cur = 0;
     long t = 0;
-    lb_launch_config cfg{4, 3, 4, 64, 1, 8};
+    lb_launch_config cfg{4, 4, 4, 64, 1, 8};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -413,6 +418,9 @@ void drop_graphs(lb_ctx* c) {
     }
 }
 
+// output columns per strip of the row-sweep schedules (3: one wavefront, 4: a workgroup)
+int strip_width(const lb_launch_config& cfg) { return cfg.schedule == 4 ? WIDE_OUT : STRIP_OUT; }
+
 lb_status upload_tiles(lb_ctx* c) {
     std::vector<TileDev> tiles;
     build_tiles(c->G, c->active, c->cfg.tile_rows, tiles);
@@ -422,7 +430,7 @@ lb_status upload_tiles(lb_ctx* c) {
         HIP_TRY(hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(), hipMemcpyHostToDevice,
                                c->stream));
     std::vector<StripDev> strips;
-    build_strips(c->G, c->active, c->cfg.chunk_rows, &strips, nullptr, c->xcd_start);
+    build_strips(c->G, c->active, c->cfg.chunk_rows, strip_width(c->cfg), &strips, nullptr, c->xcd_start);
     if ((int)strips.size() > c->L.max_strips) return fail(LB_EINVAL, "strip table overflow");
     c->nstrips = (int)strips.size();
     if (!strips.empty())
@@ -465,16 +473,24 @@ int grid_of(const lb_ctx* c) {
 
 template <int MODEL, typename MT, typename CT, typename ST = CT>
 void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid) {
-    if constexpr (MODEL == 0)
-        hipLaunchKernelGGL((lb_strip_vdw<CT>), dim3(grid), dim3(SW), 0, c->stream, a);
-    else
-        hipLaunchKernelGGL((lb_strip_bin<MT, CT, ST>), dim3(grid), dim3(SW), 0, c->stream, a);
+    const bool wide = c->cfg.schedule == 4;
+    if constexpr (MODEL == 0) {
+        if (wide)
+            hipLaunchKernelGGL((lb_wide_vdw<CT>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
+        else
+            hipLaunchKernelGGL((lb_strip_vdw<CT>), dim3(grid), dim3(SW), 0, c->stream, a);
+    } else {
+        if (wide)
+            hipLaunchKernelGGL((lb_wide_bin<MT, CT, ST>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
+        else
+            hipLaunchKernelGGL((lb_strip_bin<MT, CT, ST>), dim3(grid), dim3(SW), 0, c->stream, a);
+    }
 }
 
 // Enqueue one step (or the initialisation when init is true) from arena cur.
 void enqueue_step(lb_ctx* c, bool init) {
     if (c->ntiles == 0) return;
-    if (!init && c->cfg.schedule == 3) {
+    if (!init && (c->cfg.schedule == 3 || c->cfg.schedule == 4)) {
         if (c->nstrips == 0) return;
         StripArgs a;
         a.caps = c->d_caps;
@@ -1085,7 +1101,7 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
     if (!c || !cfg) return fail(LB_EINVAL, "null argument");
     const int r = cfg->tile_rows;
     if (r != 1 && r != 2 && r != 4 && r != 8) return fail(LB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
-    if (cfg->schedule < 0 || cfg->schedule > 3) return fail(LB_EINVAL, "schedule must be 0, 1, 2 or 3");
+    if (cfg->schedule < 0 || cfg->schedule > 4) return fail(LB_EINVAL, "schedule must be 0, 1, 2, 3 or 4");
     if (cfg->schedule == 2 && (cfg->persist_blocks_per_cu < 1 || cfg->persist_blocks_per_cu > 32))
         return fail(LB_EINVAL, "persistent workgroups per CU must be in 1..32");
     if (cfg->graph_steps != 0 && (cfg->graph_steps < 2 || cfg->graph_steps % 2 != 0 || cfg->graph_steps > 4096))
@@ -1094,7 +1110,8 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
     const int ch = cfg->chunk_rows;
     if (ch != 0 && (ch < LB_MIN_CHUNK || ch > 4096))
         return fail(LB_EINVAL, "chunk_rows must be 0 or in 4..4096");
-    const bool retile = r != c->cfg.tile_rows || cfg->chunk_rows != c->cfg.chunk_rows;
+    const bool retile = r != c->cfg.tile_rows || cfg->chunk_rows != c->cfg.chunk_rows ||
+                        strip_width(*cfg) != strip_width(c->cfg);
     c->cfg = *cfg;
     drop_graphs(c);
     if (retile) return upload_tiles(c);
@@ -1120,6 +1137,7 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     std::vector<lb_launch_config> cand;
     const int ar = orig.fp64_arith;   // the arithmetic is a choice of the caller, not tuned
     for (int ch : {6, 8, 12, 16, 32}) cand.push_back({orig.tile_rows, 3, 4, 0, ar, ch});
+    for (int ch : {8, 12, 16, 32}) cand.push_back({orig.tile_rows, 4, 4, 0, ar, ch});
     for (int r : {4, 8}) {
         cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
         cand.push_back({r, 2, 4, 0, ar, orig.chunk_rows});

@@ -158,14 +158,39 @@ __device__ __forceinline__ Planes planes_of(const float* base, int nplanes, int 
     return q;
 }
 
-// (the b32 builtins move raw 32-bit words: the float is reinterpreted, not converted)
+// (the b32 builtins move raw 32-bit words: the float is reinterpreted, not converted).
+// The scalar offset is the same in every lane; readfirstlane states so, because
+// a value the compiler keeps in a vector register would turn each access into
+// a loop over the distinct values of the lanes.
 __device__ __forceinline__ float ld(const Planes& q, int voff, int soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(q.rs, voff, soff, 0));
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_raw_buffer_load_b32(q.rs, voff, __builtin_amdgcn_readfirstlane(soff), 0));
 }
 
 __device__ __forceinline__ void st(const Planes& q, float v, int voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), q.rs, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), q.rs, voff,
+                                          __builtin_amdgcn_readfirstlane(soff), 0);
 }
+
+// 1/x for a positive normal x in the collision's arithmetic type: in FP64 the
+// hardware FP32 reciprocal (1 ulp) refined by two Newton steps (relative error
+// at the FP64 rounding level), far fewer instructions and registers than the
+// correctly rounded division; in FP32 the division itself.
+__device__ __forceinline__ double recip(double x) {
+    double r = (double)__builtin_amdgcn_rcpf((float)x);
+    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ float recip(float x) { return 1.f / x; }
+
+// Makes a uniform FP32 value opaque to loop-invariant code motion (an empty asm
+// statement that claims to modify it in its scalar register).  Material
+// constants converted to FP64 inside the sweep would otherwise be converted
+// once, before the loop, and held in a pair of vector registers for the whole
+// sweep; vector registers bound the occupancy of these kernels, the
+// conversions are cheap.
+__device__ __forceinline__ void uniform_opaque(float& v) { asm volatile("" : "+s"(v)); }
 
 // Pull of the lane's node on a row (bounce-back for solid sources).  Straight-line
 // code, the source chosen by selects: a branch around the loads (even a uniform
@@ -349,7 +374,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
             const Mom<CT> mc{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
             const CT F_cur = sm_cur ? CT(0) : (CT)c.Fx;
             const CT rho_c = (CT)c.rho_ref + mc.drho;
-            const CT inv_rho = CT(1) / rho_c;
+            const CT inv_rho = recip(rho_c);
             const CT ux_cur = (mc.jx + CT(0.5) * F_cur) * inv_rho, uy_cur = mc.jy * inv_rho;
             const CT ph = (CT)phi, phib = (CT)c.phib;
             const CT dX = mc.drho * (CT(1) / CT(3)) +
@@ -366,6 +391,9 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
+            // the phi update below is not to be interleaved with the collision
+            // (its LDS reads would be hoisted into the collision's register peak)
+            __builtin_amdgcn_sched_barrier(0);
             // phi(t+1) = phi(t) + sum_i g^eq_i(source of i) - sum_i g^eq_i(r), i >= 1.
             // With g^eq_i = w_i (A + phi e_i.u (1 + 3/2 e_i.u)), A = Gamma mu - phi |u|^2 / 2,
             // sum_i w_i = 5/3 and sum_i w_i (e_i.u)^2 = |u|^2 (Appendix A moments), this is
@@ -471,29 +499,39 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
         wave_sync();
         if (out_col && fl_cur) {
             float dxf, dyf, lapf;
+            // constants of the FP64 part, converted where used (see uniform_opaque)
+            CapDev cd = c;
+            uniform_opaque(cd.Fx);
+            uniform_opaque(cd.rho_ref);
+            uniform_opaque(cd.T);
+            uniform_opaque(cd.a);
+            uniform_opaque(cd.b);
+            uniform_opaque(cd.ibr);
+            uniform_opaque(cd.kappa);
+            uniform_opaque(cd.omega_l);
             stencil3(Q[r3(-1)], Q[r3(0)], Q[r3(1)], k, sm_cur, G2, dxf, dyf, lapf);
             const bool bnd = sm_cur != 0u;
-            const CT F = bnd ? CT(0) : (CT)c.Fx;
+            const CT F = bnd ? CT(0) : (CT)cd.Fx;
             CT fcur[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) fcur[i] = (CT)f[i];
             const Mom<CT> m = moments_of(fcur, bnd);
-            const CT rho_ref = (CT)c.rho_ref;
+            const CT rho_ref = (CT)cd.rho_ref;
             const CT rho = rho_ref + m.drho;
-            const CT inv_rho = CT(1) / rho;
+            const CT inv_rho = recip(rho);
             const CT ux = (m.jx + CT(0.5) * F) * inv_rho;
             const CT uy = m.jy * inv_rho;
-            const CT T = (CT)c.T, av = (CT)c.a;
-            const CT ib = CT(1) / (CT(1) - (CT)c.b * rho);
-            const CT dX = m.drho * (T * ib * (CT)c.ibr - av * (rho + rho_ref)) - (CT)c.kappa * rho * (CT)lapf;
-            const CT omega = (CT)c.omega_l;
+            const CT T = (CT)cd.T, av = (CT)cd.a;
+            const CT ib = recip(CT(1) - (CT)cd.b * rho);
+            const CT dX = m.drho * (T * ib * (CT)cd.ibr - av * (rho + rho_ref)) - (CT)cd.kappa * rho * (CT)lapf;
+            const CT omega = (CT)cd.omega_l;
             CT lam = CT(0);
-            if (c.lam_on != 0.f) {
+            if (cd.lam_on != 0.f) {
                 const CT dp0 = T * ib * ib - CT(2) * av * rho;
-                lam = (CT(1) / omega - CT(0.5)) * (CT(1) / CT(3) - dp0);
+                lam = (recip(omega) - CT(0.5)) * (CT(1) / CT(3) - dp0);
             }
             CT o[9];
-            collide(c, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
+            collide(cd, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);

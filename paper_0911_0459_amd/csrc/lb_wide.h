@@ -1,0 +1,387 @@
+// Cooperative row-sweep ("wide strip") kernels of lbcap: the time step of
+// lb_strip_bin / lb_strip_vdw with every wavefront's output columns aligned to
+// whole 256-byte row segments.
+//
+// A workgroup owns the WIDE_OUT = 192 output columns xs .. xs+191 of a chunk of
+// rows (xs a multiple of 192; rows are pitched to 64 floats, so each wavefront
+// stores whole cache lines and no line is shared with another workgroup) and
+// marches along y as the single-wave strips do.  Its NWM = 3 main wavefronts
+// produce the outputs, one column per lane.  The step at a column needs the
+// velocity and the chemical potential one column to either side and the order
+// field two columns to either side: a fourth (halo) wavefront computes the
+// velocity and the chemical potential of the columns xs-1 and xs+192 (lanes 0
+// and 1) and loads the order field of xs-2 and xs+193 (lanes 2 and 3); its
+// other lanes repeat lane 0's loads and store nothing.  Four wavefronts per
+// workgroup spread evenly over the four SIMDs of a CU.
+//
+// Rows of phi, u and mu live in LDS rings shared by the four wavefronts.  The
+// wavefronts meet at LDS-only barriers (two per row for the binary model, one
+// for van der Waals); the rings hold one row more than a row's stencils read,
+// so a wavefront that has passed a row's last barrier can already fill the
+// next row's slots while the others still read the current ones.  The
+// population loads requested one row ahead stay in flight across the barriers.
+#pragma once
+#include "lb_strip.h"
+
+namespace lbk {
+
+constexpr int WIDE_OUT = 192;                  // output columns per wide strip
+constexpr int NWM = WIDE_OUT / SW;             // main wavefronts
+constexpr int WIDE_THREADS = (NWM + 1) * SW;   // main wavefronts and the halo wavefront
+constexpr int WU = WIDE_OUT + 2;               // u / mu row: columns xs-1 .. xs+WIDE_OUT
+constexpr int WP = WIDE_OUT + 4;               // phi row: columns xs-2 .. xs+WIDE_OUT+1
+
+// Workgroup barrier that orders LDS accesses only.  __syncthreads() would also
+// wait for every outstanding global load, including the row requested ahead.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Role of a thread of a wide strip.
+struct WideLane {
+    int dx;     // its column minus xs (wrapped periodically by lane_cols)
+    int uj;     // index of its column in a u / mu row (0 for lanes that compute none)
+    int pj;     // index of its column in a phi row
+    bool main;  // a main wavefront lane: one output column
+    bool um;    // computes u and mu (main lanes; halo lanes 0 and 1)
+    bool ph;    // stores phi (main lanes; halo lanes 0..3)
+};
+
+__device__ __forceinline__ WideLane wide_lane() {
+    const int w = threadIdx.x >> 6, k = threadIdx.x & (SW - 1);
+    WideLane r;
+    if (w < NWM) {
+        r.dx = SW * w + k;
+        r.main = r.um = r.ph = true;
+    } else {
+        r.dx = k == 1 ? WIDE_OUT : (k == 2 ? -2 : (k == 3 ? WIDE_OUT + 1 : -1));
+        r.main = false;
+        r.um = k < 2;
+        r.ph = k < 4;
+    }
+    r.uj = r.um ? r.dx + 1 : 0;
+    r.pj = r.dx + 2;
+    return r;
+}
+
+// ---- binary model --------------------------------------------------------------
+// Reads f*(t-1) and phi(t) of one wide strip chunk, writes f*(t) and phi(t+1).
+// (at most 80 vector registers: six wavefronts per SIMD, six workgroups per CU)
+template <typename MT, typename CT, typename ST = CT>
+__global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
+    const int si = strip_index(a);
+    if (si < 0) return;
+    const StripDev s = a.strips[si];
+    const CapDev c = a.caps[s.cap];
+    const Geo g = geo_of(c);
+    const int P = (int)c.plane;
+    const int sb = a.cur ^ c.par;
+    const Planes fs = planes_of((sb ? a.arena1 : a.arena0) + c.off_f, 9, P, c.pitch);
+    const Planes ps = planes_of((sb ? a.arena1 : a.arena0) + c.off_phi, 1, P, c.pitch);
+    const Planes fd = planes_of((sb ? a.arena0 : a.arena1) + c.off_f, 9, P, c.pitch);
+    const Planes pd = planes_of((sb ? a.arena0 : a.arena1) + c.off_phi, 1, P, c.pitch);
+
+    // ring slots: row y of the phi ring is y mod 8, of the u / mu rings y mod 4
+    __shared__ float PH[8][WP];
+    // velocity and Gamma mu - phi |u|^2 / 2, the part of g^eq that does not
+    // depend on the direction
+    __shared__ float UX[4][WU], UY[4][WU], AM[4][WU];
+
+    const WideLane W = wide_lane();
+    const int xl = s.xs + W.dx;
+    const LaneCols L = lane_cols(g, xl);
+    const bool out_col = W.main && xl < g.nx;
+    const int uj = W.uj, pj = W.pj;
+    const float G2 = 2.f * c.G;
+    const float kap = c.kappa, Gam = c.Gamma;
+    auto s8 = [](int y) { return y & 7; };   // y >= -2: rows are offset by 8 below
+    auto s4 = [](int y) { return y & 3; };
+
+    // phi is loaded unconditionally (solid nodes have valid addresses) and
+    // masked when stored, so that no instruction waits on it early
+    auto phi_load = [&](const RowInfo& r) { return ld(ps, L.b0, r.y0 * ps.rb); };
+    auto phi_store = [&](int sl, const RowInfo& r, float m) {
+        if (W.ph) PH[sl][pj] = (L.t0 && r.w0) ? 0.f : m;
+    };
+    // moments of a pulled row (FP32, kept by the caller) and its velocity into LDS
+    auto u_row = [&](int sl, const float (&f)[9], bool fluid, unsigned sm, Mom<float>& m) {
+        float ux = 0.f, uy = 0.f;
+        if (fluid) {
+            const bool bnd = sm != 0u;
+            m = moments_of(f, bnd);
+            const float F = bnd ? 0.f : c.Fx;
+            const float inv_rho = 1.f / (c.rho_ref + m.drho);
+            ux = (m.jx + 0.5f * F) * inv_rho;
+            uy = m.jy * inv_rho;
+        } else {
+            m = Mom<float>{0.f, 0.f, 0.f, 0.f, 0.f};
+        }
+        if (W.um) {
+            UX[sl][uj] = ux;
+            UY[sl][uj] = uy;
+        }
+    };
+    // stencils of phi (rows pm, p0, pp), Gamma mu and the direction-free part of g^eq
+    auto mu_row = [&](int sl, int pm, int p0, int pp, bool fluid, unsigned sm, float& dx, float& dy, float& lap) {
+        float v = 0.f;
+        dx = dy = lap = 0.f;
+        if (fluid) {
+            stencil3(PH[pm], PH[p0], PH[pp], uj + 1, sm, G2, dx, dy, lap);
+            const float ph = PH[p0][uj + 1];
+            const float gmu = Gam * (mu_bulk(c, ph) - kap * lap);
+            const float ux = UX[sl][uj], uy = UY[sl][uj];
+            v = gmu - 0.5f * ph * (ux * ux + uy * uy);
+        }
+        if (W.um) AM[sl][uj] = v;
+    };
+
+    // rows are addressed in the rings as y + 8 (y >= ya - 2 >= -2)
+    const int yo = 8;
+    // ---- prologue: phi rows ya-2..ya+1; u, mu of rows ya-1, ya
+    for (int d = -2; d <= 1; ++d) {
+        const RowInfo rr = row_info(g, s.ya + d);
+        phi_store(s8(s.ya + d + yo), rr, phi_load(rr));
+    }
+    float f[9];
+    Mom<float> mom_cur;
+    RowInfo ri = row_info(g, s.ya - 1);
+    unsigned sm = solid_bits(L, ri);
+    bool fl = !(L.t0 && ri.w0);
+    pull_lane(fs, L, ri, sm, f);
+    u_row(s4(s.ya - 1 + yo), f, fl, sm, mom_cur);
+    ri = row_info(g, s.ya);
+    unsigned sm_cur = solid_bits(L, ri);
+    bool fl_cur = !(L.t0 && ri.w0);
+    pull_lane(fs, L, ri, sm_cur, f);
+    u_row(s4(s.ya + yo), f, fl_cur, sm_cur, mom_cur);
+    lds_barrier();
+    float dx_cur, dy_cur, lap_cur, t0, t1, t2;
+    mu_row(s4(s.ya - 1 + yo), s8(s.ya - 2 + yo), s8(s.ya - 1 + yo), s8(s.ya + yo), fl, sm, t0, t1, t2);
+    mu_row(s4(s.ya + yo), s8(s.ya - 1 + yo), s8(s.ya + yo), s8(s.ya + 1 + yo), fl_cur, sm_cur, dx_cur, dy_cur,
+           lap_cur);
+    // Requests run one row ahead of the arithmetic; the two request buffers swap
+    // roles every row (the loop is unrolled by two), so a finished request is
+    // never copied: a copy would wait for every load in flight.
+    struct Ahead {
+        float f[9];       // pulled populations of row y+1
+        float pm;         // phi of row y+2
+        RowInfo rph;      // row y+2
+        unsigned sm;
+        bool fl;
+    };
+    Ahead A, B;
+    {
+        const RowInfo rn = row_info(g, s.ya + 1);
+        A.sm = solid_bits(L, rn);
+        A.fl = !(L.t0 && rn.w0);
+        pull_lane(fs, L, rn, A.sm, A.f);
+        A.rph = row_info(g, s.ya + 2);
+        A.pm = phi_load(A.rph);
+    }
+
+    // one row y: n holds the requests for row y+1, p receives those for row y+2
+    auto iter = [&](int y, Ahead& n, Ahead& p) {
+        const int yr = y + yo;
+        // (a) requests for the next row: row y+2 pulled, phi row y+3 (in the last
+        // row of the chunk a repeat of the previous requests: cache hits, unused)
+        const int ya2 = y + 1 < s.yb ? y + 2 : y + 1;
+        const RowInfo ri_p = row_info(g, ya2);
+        p.sm = solid_bits(L, ri_p);
+        p.fl = !(L.t0 && ri_p.w0);
+        p.rph = row_info(g, ya2 + 1);
+        pull_lane(fs, L, ri_p, p.sm, p.f);
+        p.pm = phi_load(p.rph);
+        __builtin_amdgcn_sched_barrier(0);
+        // (b) phi row y+2; u and moments of row y+1
+        phi_store(s8(yr + 2), n.rph, n.pm);
+        Mom<float> mom_n;
+        u_row(s4(yr + 1), n.f, n.fl, n.sm, mom_n);
+        lds_barrier();
+        // (c) stencils and mu of row y+1
+        float dx_n, dy_n, lap_n;
+        mu_row(s4(yr + 1), s8(yr), s8(yr + 1), s8(yr + 2), n.fl, n.sm, dx_n, dy_n, lap_n);
+        lds_barrier();
+        // (d) collision and phi update of row y (main lanes)
+        if (out_col && fl_cur) {
+            // constants of the FP64 part, converted where used (see uniform_opaque)
+            CapDev cd = c;
+            uniform_opaque(cd.kappa);
+            uniform_opaque(cd.Fx);
+            uniform_opaque(cd.rho_ref);
+            uniform_opaque(cd.phib);
+            uniform_opaque(cd.B);
+            const int p0 = s8(yr), u0 = s4(yr);
+            const float phi = PH[p0][pj];
+            const Mom<CT> mc{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
+            const CT F_cur = sm_cur ? CT(0) : (CT)cd.Fx;
+            const CT rho_c = (CT)cd.rho_ref + mc.drho;
+            const CT inv_rho = recip(rho_c);
+            const CT ux_cur = (mc.jx + CT(0.5) * F_cur) * inv_rho, uy_cur = mc.jy * inv_rho;
+            const CT ph = (CT)phi, phib = (CT)cd.phib;
+            const CT dX = mc.drho * (CT(1) / CT(3)) +
+                          CT(0.25) * (CT)cd.B * ((ph - phib) * (ph + phib)) * (CT(3) * ph * ph + phib * phib) -
+                          (CT)cd.kappa * ph * (CT)lap_cur;
+            // the relaxation rate only scales the shear stresses (FP32) and the
+            // forcing term: FP32 with the hardware reciprocal (1 ulp)
+            const float pc = phi < -1.f ? -1.f : (phi > 1.f ? 1.f : phi);
+            const float nu = cd.nu_g + 0.5f * (pc + 1.f) * (cd.nu_l - cd.nu_g);
+            const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
+            CT o[9];
+            collide<CT, ST>(cd, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            const int srow = row_info(g, y).y0 * fd.rb;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
+            // the phi update below is not to be interleaved with the collision
+            // (its LDS reads would be hoisted into the collision's register peak)
+            __builtin_amdgcn_sched_barrier(0);
+            // phi(t+1) = phi(t) + sum_i [g^eq_i(r - e_i) - g^eq_i(r)], i >= 1, with the
+            // direction-free part A = Gamma mu - phi |u|^2 / 2 taken as differences
+            // (exactly zero in a uniform region), as in lb_strip_bin
+            const float uxf = UX[u0][uj], uyf = UY[u0][uj];
+            const float am = AM[u0][uj];
+            auto adv = [&](int i, float pp, float ax, float ay) {
+                const float eu = (float)ex_(i) * ax + (float)ey_(i) * ay;
+                return pp * eu * (1.f + 1.5f * eu);
+            };
+            float sa = 0.f, sd = 0.f;   // axis and diagonal sums
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                float t;
+                if ((sm_cur >> opp_(i)) & 1u) {
+                    t = adv(opp_(i), phi, uxf, uyf);   // bounce-back of g*_opp(i)(r): no A difference
+                } else {
+                    const int su = s4(yr - ey_(i)), sp = s8(yr - ey_(i));
+                    const int ku = uj - ex_(i), kp = pj - ex_(i);
+                    t = (AM[su][ku] - am) + adv(i, PH[sp][kp], UX[su][ku], UY[su][ku]);
+                }
+                if (i <= 4) sa += t;
+                else sd += t;
+            }
+            const float dphi = (sa * (1.f / 3.f) + sd * (1.f / 12.f)) - 1.5f * phi * (uxf * uxf + uyf * uyf);
+            st(pd, phi + dphi, L.b0, srow);
+        }
+        // (e) rotate the row state
+        mom_cur = mom_n;
+        sm_cur = n.sm;
+        fl_cur = n.fl;
+        dx_cur = dx_n;
+        dy_cur = dy_n;
+        lap_cur = lap_n;
+    };
+    for (int y = s.ya; y < s.yb; y += 2) {
+        iter(y, A, B);
+        if (y + 1 >= s.yb) break;
+        iter(y + 1, B, A);
+    }
+}
+
+// ---- van der Waals model ---------------------------------------------------------
+template <typename CT>
+__global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
+    const int si = strip_index(a);
+    if (si < 0) return;
+    const StripDev s = a.strips[si];
+    const CapDev c = a.caps[s.cap];
+    const Geo g = geo_of(c);
+    const int P = (int)c.plane;
+    const int sb = a.cur ^ c.par;
+    const Planes fs = planes_of((sb ? a.arena1 : a.arena0) + c.off_f, 9, P, c.pitch);
+    const Planes fd = planes_of((sb ? a.arena0 : a.arena1) + c.off_f, 9, P, c.pitch);
+
+    __shared__ float Q[4][WU];   // drho rows; row y in slot y mod 4
+    const WideLane W = wide_lane();
+    const int xl = s.xs + W.dx;
+    const LaneCols L = lane_cols(g, xl);
+    const bool out_col = W.main && xl < g.nx;
+    const int uj = W.uj;
+    const float G2 = 2.f * c.G;
+    const int yo = 4;   // rows are addressed in the ring as y + 4 (y >= ya - 1 >= -1)
+    auto s4 = [](int y) { return y & 3; };
+    auto q_store = [&](int sl, bool fluid, const float (&f)[9]) {
+        if (W.um) Q[sl][uj] = fluid ? sum9(f) : 0.f;
+    };
+
+    // three population buffers rotate (current row, row y+1, request for row y+2);
+    // the loop is unrolled by three so that no finished request is copied
+    float fa[9], fb[9], fc[9];
+    RowInfo ri = row_info(g, s.ya - 1);
+    bool fl = !(L.t0 && ri.w0);
+    pull_lane(fs, L, ri, solid_bits(L, ri), fa);
+    q_store(s4(s.ya - 1 + yo), fl, fa);
+    ri = row_info(g, s.ya);
+    unsigned sm_cur = solid_bits(L, ri);
+    bool fl_cur = !(L.t0 && ri.w0);
+    pull_lane(fs, L, ri, sm_cur, fa);
+    q_store(s4(s.ya + yo), fl_cur, fa);
+    RowInfo ri_n = row_info(g, s.ya + 1);
+    unsigned sm_n = solid_bits(L, ri_n);
+    bool fl_n = !(L.t0 && ri_n.w0);
+    pull_lane(fs, L, ri_n, sm_n, fb);
+
+    auto iter = [&](int y, const float (&f)[9], const float (&fn)[9], float (&fp)[9]) {
+        const int yr = y + yo;
+        // request for row y+2 (in the last row of the chunk a repeat of the
+        // previous one: cache hits, unused)
+        const RowInfo ri_p = row_info(g, y + 1 < s.yb ? y + 2 : y + 1);
+        const unsigned sm_p = solid_bits(L, ri_p);
+        const bool fl_p = !(L.t0 && ri_p.w0);
+        pull_lane(fs, L, ri_p, sm_p, fp);
+        __builtin_amdgcn_sched_barrier(0);
+        q_store(s4(yr + 1), fl_n, fn);
+        lds_barrier();
+        if (out_col && fl_cur) {
+            float dxf, dyf, lapf;
+            // constants of the FP64 part, converted where used (see uniform_opaque)
+            CapDev cd = c;
+            uniform_opaque(cd.Fx);
+            uniform_opaque(cd.rho_ref);
+            uniform_opaque(cd.T);
+            uniform_opaque(cd.a);
+            uniform_opaque(cd.b);
+            uniform_opaque(cd.ibr);
+            uniform_opaque(cd.kappa);
+            uniform_opaque(cd.omega_l);
+            stencil3(Q[s4(yr - 1)], Q[s4(yr)], Q[s4(yr + 1)], uj, sm_cur, G2, dxf, dyf, lapf);
+            const bool bnd = sm_cur != 0u;
+            const CT F = bnd ? CT(0) : (CT)cd.Fx;
+            CT fcur[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fcur[i] = (CT)f[i];
+            const Mom<CT> m = moments_of(fcur, bnd);
+            const CT rho_ref = (CT)cd.rho_ref;
+            const CT rho = rho_ref + m.drho;
+            const CT inv_rho = recip(rho);
+            const CT ux = (m.jx + CT(0.5) * F) * inv_rho;
+            const CT uy = m.jy * inv_rho;
+            const CT T = (CT)cd.T, av = (CT)cd.a;
+            const CT ib = recip(CT(1) - (CT)cd.b * rho);
+            const CT dX = m.drho * (T * ib * (CT)cd.ibr - av * (rho + rho_ref)) - (CT)cd.kappa * rho * (CT)lapf;
+            const CT omega = (CT)cd.omega_l;
+            CT lam = CT(0);
+            if (cd.lam_on != 0.f) {
+                const CT dp0 = T * ib * ib - CT(2) * av * rho;
+                lam = (recip(omega) - CT(0.5)) * (CT(1) / CT(3) - dp0);
+            }
+            CT o[9];
+            collide(cd, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
+            const int srow = row_info(g, y).y0 * fd.rb;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
+        }
+        sm_cur = sm_n;
+        fl_cur = fl_n;
+        sm_n = sm_p;
+        fl_n = fl_p;
+    };
+    for (int y = s.ya; y < s.yb; y += 3) {
+        iter(y, fa, fb, fc);
+        if (y + 1 >= s.yb) break;
+        iter(y + 1, fb, fc, fa);
+        if (y + 2 >= s.yb) break;
+        iter(y + 2, fc, fa, fb);
+    }
+}
+
+}  // namespace lbk

@@ -85,6 +85,9 @@ SHAPES = [
     dict(tile_rows=8, schedule=1, persist_blocks_per_cu=4, graph_steps=16, fp64_arith=0),
     dict(schedule=3, chunk_rows=0, graph_steps=64, fp64_arith=1),
     dict(schedule=3, chunk_rows=8, graph_steps=0, fp64_arith=0),
+    dict(schedule=4, chunk_rows=0, graph_steps=64, fp64_arith=1),
+    dict(schedule=4, chunk_rows=8, graph_steps=0, fp64_arith=0),
+    dict(schedule=4, chunk_rows=5, graph_steps=2, fp64_arith=1),
 ]
 
 
@@ -103,6 +106,28 @@ def test_ragged_lattice_short_run(L, model, cfg):
     gpu, _ = gpu_run(L, w, 300, cfg=cfg)
     orc, _ = run_oracle(w, 300)
     drho, dphi, du = field_errors(w, gpu, orc)
+    assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (drho, dphi, du)
+
+
+@pytest.mark.parametrize("model", ["vdw", "binary"])
+def test_wide_strips_across_strip_boundaries(L, model):
+    """700x45 lattice: four 192-column strips (the inlet inside the second,
+    two tube-only strips, the last one ragged and ending with the tube),
+    against the oracle and bitwise against the one-wavefront strips."""
+    g = I.Geometry(nx=700, ny=45, x_in=250, tube_len=450, tube_h=17, y0=14)
+    if model == "vdw":
+        w = I.Workload("vdw_wide", "vdw", g, 0, 0, seed=31, nu_l=0.13, nu_g=0.13, wall_grad=-0.1,
+                       liquid=4.5, gas=2.6, **I.VDW_CONSTS)
+    else:
+        nl, ng = I.viscosity_pair(20.0)
+        w = I.Workload("bin_wide", "binary", g, 0, 0, seed=32, nu_l=nl, nu_g=ng, theta_deg=50.0,
+                       liquid=1.0, gas=-1.0, **I.BIN_CONSTS)
+    wide, _ = gpu_run(L, w, 200, cfg=dict(schedule=4, chunk_rows=8, fp64_arith=1))
+    narrow, _ = gpu_run(L, w, 200, cfg=dict(schedule=3, chunk_rows=8, fp64_arith=1))
+    for x, y in zip(wide, narrow):
+        assert np.array_equal(x, y)
+    orc, _ = run_oracle(w, 200)
+    drho, dphi, du = field_errors(w, wide, orc)
     assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (drho, dphi, du)
 
 
@@ -183,6 +208,12 @@ def test_bitwise_determinism_and_launch_shape_independence(L):
     e, _ = gpu_run(L, w, 200, cfg=dict(schedule=3, chunk_rows=16, fp64_arith=1))
     for x, y in zip(d, e):
         assert np.array_equal(x, y)
+    # workgroup-wide strips evaluate every node with the same expressions as the
+    # one-wavefront strips
+    f, _ = gpu_run(L, w, 200, cfg=dict(schedule=4, chunk_rows=0, fp64_arith=1))
+    h, _ = gpu_run(L, w, 200, cfg=dict(schedule=4, chunk_rows=12, fp64_arith=1))
+    for x, y, z in zip(d, f, h):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
 
 
 def test_checkpoint_resume_is_bitwise(L):
@@ -280,7 +311,7 @@ def test_autotune_keeps_state(L):
     cfg0 = a.launch_config()
     a.step(40)
     cfg, us = a.autotune(trial_steps=6)
-    assert cfg.schedule in (0, 1, 2, 3) and us > 0
+    assert cfg.schedule in (0, 1, 2, 3, 4) and us > 0
     assert a.t == 40
     a.step(60)
     # a new lattice of this size class starts from the tuned shape: replay a's history
@@ -356,7 +387,7 @@ def test_graph_replays_equal_direct_launches(L):
     w = small_binary(nx=300, ny=64, H=24)
     p = L.params_from_workload(w, wall_grad=oracle_wall_grad(w))
     g = L.geometry_from_workload(w)
-    for shape in (dict(schedule=3, chunk_rows=8), dict(tile_rows=4, schedule=1)):
+    for shape in (dict(schedule=3, chunk_rows=8), dict(schedule=4, chunk_rows=8), dict(tile_rows=4, schedule=1)):
         direct = L.Lattice(p, g, w.initial_field())
         direct.set_launch_config(**shape, graph_steps=0)
         direct.step(300)
