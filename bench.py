@@ -42,9 +42,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel: str, workload: str):
+def traffic_from_profiles(kernel: str, workload: str, launch: dict):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if absent or taken on another version of the kernel source."""
+    None if absent, taken on another version of the kernel source or taken
+    with another strip chunking or arithmetic."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.json")
     if not os.path.exists(path):
         return None
@@ -53,6 +54,9 @@ def traffic_from_profiles(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    taken = d.get("launch", {})
+    if any(taken.get(k) != launch.get(k) for k in ("schedule", "chunk_rows", "fp64_arith", "tile_rows")):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -222,7 +226,7 @@ def main():
     achieved = bpl * fluid / (us_kernel * 1e-6) / 1e9 if us_kernel > 0 else None
     kname = ({3: "lb_strip_", 4: "lb_wide_"}[cfg.schedule] + ("bin" if model == "binary" else "vdw")
              if cfg.schedule in (3, 4) else f"lb_step_kernel_{model}_{cfg.tile_rows}")
-    traffic = traffic_from_profiles(kname, args.workload)
+    traffic = traffic_from_profiles(kname, args.workload, cfg.asdict())
     config.update({"model": model, "fluid_nodes": fluid, "launch": cfg.asdict(), "bytes_per_lup": bpl})
     out = {
         "metric": "MLUPS (fluid-node updates/s) and fraction of HBM roofline",

@@ -159,6 +159,7 @@ int count_tiles(const lb_geometry& g, int rows) {
 // Strips of STRIP_OUT output columns; a strip lying entirely in the tube
 // section only covers the channel rows.  chunk = 0 keeps whole strips.
 constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
+constexpr size_t LB_STRIP_GROUP = 16;  // neighbouring strip columns listed chunk by chunk
 
 // Strip table of the row-sweep kernels.  Every strip column (width output
 // columns of one capillary, over the rows that hold fluid) is cut into chunks:
@@ -167,7 +168,9 @@ constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
 // contiguous runs of about equal row count; each XCD's run lists the long
 // chunks of its columns first and the short ones last, so the end of a step is
 // made of short strips (a small tail) while most rows go through long strips
-// (few prologues), and the chunks of one column share an L2.
+// (few prologues), and the chunks of one column share an L2.  Within a run,
+// groups of LB_STRIP_GROUP neighbouring columns are listed chunk by chunk
+// across the group, so that strips sharing halo columns run at the same time.
 // xcd_start[x] .. xcd_start[x + 1] is XCD x's run.
 void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk, int width,
                   std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
@@ -197,22 +200,38 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
         if (xcd_start) xcd_start[x] = n;
         const long long goal = rows * (x + 1) / 8;
         tails.clear();
-        for (; ci < cols.size() && (done < goal || x == 7); ++ci) {
-            const Col& c = cols[ci];
-            done += c.yb - c.ya;
+        const size_t c0 = ci;
+        for (; ci < cols.size() && (done < goal || x == 7); ++ci) done += cols[ci].yb - cols[ci].ya;
+        // groups of LB_STRIP_GROUP neighbouring columns, chunk by chunk across the group
+        for (size_t g0 = c0; g0 < ci; g0 += LB_STRIP_GROUP) {
+            const size_t g1 = std::min(ci, g0 + LB_STRIP_GROUP);
             if (chunk <= 0) {
-                if (out) out->push_back(StripDev{c.cap, c.xs, c.ya, c.yb});
-                ++n;
+                for (size_t j = g0; j < g1; ++j) {
+                    if (out) out->push_back(StripDev{cols[j].cap, cols[j].xs, cols[j].ya, cols[j].yb});
+                    ++n;
+                }
                 continue;
             }
-            const int tail = chunk < 16 ? 0 : std::min(c.yb - c.ya, 2 * small);
-            for (int y = c.ya; y < c.yb - tail; y += chunk) {
-                if (out) out->push_back(StripDev{c.cap, c.xs, y, std::min(y + chunk, c.yb - tail)});
-                ++n;
+            for (int k = 0;; ++k) {
+                bool any = false;
+                for (size_t j = g0; j < g1; ++j) {
+                    const Col& c = cols[j];
+                    const int tail = chunk < 16 ? 0 : std::min(c.yb - c.ya, 2 * small);
+                    const int y = c.ya + k * chunk;
+                    if (y >= c.yb - tail) continue;
+                    any = true;
+                    if (out) out->push_back(StripDev{c.cap, c.xs, y, std::min(y + chunk, c.yb - tail)});
+                    ++n;
+                }
+                if (!any) break;
             }
-            for (int y = c.yb - tail; y < c.yb; y += small) {
-                tails.push_back(StripDev{c.cap, c.xs, y, std::min(y + small, c.yb)});
-                ++n;
+            for (size_t j = g0; j < g1; ++j) {
+                const Col& c = cols[j];
+                const int tail = chunk < 16 ? 0 : std::min(c.yb - c.ya, 2 * small);
+                for (int y = c.yb - tail; y < c.yb; y += small) {
+                    tails.push_back(StripDev{c.cap, c.xs, y, std::min(y + small, c.yb)});
+                    ++n;
+                }
             }
         }
         if (out) out->insert(out->end(), tails.begin(), tails.end());

@@ -83,7 +83,12 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     const Planes fd = planes_of((sb ? a.arena0 : a.arena1) + c.off_f, 9, P, c.pitch);
     const Planes pd = planes_of((sb ? a.arena0 : a.arena1) + c.off_phi, 1, P, c.pitch);
 
-    // ring slots: row y of the phi ring is y mod 8, of the u / mu rings y mod 4
+    // ring slots: row y of the phi ring is y mod 8, of the u / mu rings y mod 4.
+    // No barrier ends a row: a wavefront that has passed row y's second barrier
+    // and starts row y+1 writes phi row y+3 (slot y-5 mod 8) and u row y+2 (slot
+    // y-2 mod 4), while a slower one may still be in row y's last phase reading
+    // phi, u and mu rows y-1..y+1; and it waits at row y+1's first barrier
+    // before it writes mu row y+2, which row y's last phase no longer reads.
     __shared__ float PH[8][WP];
     // velocity and Gamma mu - phi |u|^2 / 2, the part of g^eq that does not
     // depend on the direction
@@ -290,7 +295,10 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
     const Planes fs = planes_of((sb ? a.arena1 : a.arena0) + c.off_f, 9, P, c.pitch);
     const Planes fd = planes_of((sb ? a.arena0 : a.arena1) + c.off_f, 9, P, c.pitch);
 
-    __shared__ float Q[4][WU];   // drho rows; row y in slot y mod 4
+    // drho rows, row y in slot y mod 4: a wavefront that has passed row y's
+    // barrier writes row y+2 (slot y-2 mod 4) while a slower one still reads rows
+    // y-1..y+1, then waits at row y+1's barrier
+    __shared__ float Q[4][WU];
     const WideLane W = wide_lane();
     const int xl = s.xs + W.dx;
     const LaneCols L = lane_cols(g, xl);
