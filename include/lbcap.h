@@ -229,7 +229,8 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    4 (default) the same row sweep with a workgroup per strip of 192 output columns
  *    aligned to the row pitch (three wavefronts of 64 output columns and one
  *    that supplies the two neighbour columns), so that no stored cache line is
- *    shared between workgroups; bitwise the same results as 3.
+ *    shared between workgroups.  The same arithmetic as 3, compiled apart:
+ *    the results agree to the last bits (vdW bitwise, binary within 3e-7).
  *    0..2 tiles of 64 x tile_rows nodes with the order field recomputed on a
  *    halo: 0 one workgroup per tile in table order, 1 tiles grouped per XCD,
  *    2 persistent workgroups (persist_blocks_per_cu x 256 CUs) striding the table.

@@ -490,6 +490,11 @@ int grid_of(const lb_ctx* c) {
     return n;
 }
 
+// Extra (unused) LDS per one-wavefront binary strip: with it at most 16 strips
+// share a CU (4 wavefronts per SIMD), which measured faster than the 5 that
+// its registers would allow.
+constexpr size_t STRIP_BIN_LDS_PAD = 6 * 1024;
+
 template <int MODEL, typename MT, typename CT, typename ST = CT>
 void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid) {
     const bool wide = c->cfg.schedule == 4;
@@ -502,7 +507,7 @@ void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid) {
         if (wide)
             hipLaunchKernelGGL((lb_wide_bin<MT, CT, ST>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
         else
-            hipLaunchKernelGGL((lb_strip_bin<MT, CT, ST>), dim3(grid), dim3(SW), 0, c->stream, a);
+            hipLaunchKernelGGL((lb_strip_bin<MT, CT, ST>), dim3(grid), dim3(SW), STRIP_BIN_LDS_PAD, c->stream, a);
     }
 }
 

@@ -206,17 +206,20 @@ __device__ __forceinline__ R mu_bulk(const CapDev& c, R phi) {
 //   m:   pre-collision moments (rho - rho_ref, j after rest, pxx, pxy)
 //   dX:  X - X_ref, X = p0 - kappa q lap(q) the isotropic part of Eq. (equilibrium)
 //   lam: Galilean-term coefficient; dq: gradient of q; F: body force on this node
-template <typename R, typename S = R>
+// LAM = false drops the Galilean terms at compile time (lam must then be 0, as
+// in the binary model); the results are the same, with fewer instructions.
+template <typename R, typename S = R, bool LAM = true>
 __device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX, R lam, R omega,
                                         R dxq, R dyq, R F, R (&o)[9]) {
     const R kappa = (R)c.kappa;
-    const R udq = ux * dxq + uy * dyq;
-    const R trQ = rho * (ux * ux + uy * uy) + R(4) * lam * udq;
+    const R u2 = rho * (ux * ux + uy * uy);
+    const R trQ = LAM ? u2 + R(4) * lam * (ux * dxq + uy * dyq) : u2;
     const R grad2 = dxq * dxq + dyq * dyq;
     // traceless stresses of the equilibrium and their relaxation in S
     const S sux = (S)ux, suy = (S)uy, sdx = (S)dxq, sdy = (S)dyq, srho = (S)rho, slam = (S)lam;
-    const S dQ = srho * (sux * sux - suy * suy) + S(2) * slam * (sux * sdx - suy * sdy);
-    const S Qxy = srho * sux * suy + slam * (sux * sdy + suy * sdx);
+    const S dQ0 = srho * (sux * sux - suy * suy), Qxy0 = srho * sux * suy;
+    const S dQ = LAM ? dQ0 + S(2) * slam * (sux * sdx - suy * sdy) : dQ0;
+    const S Qxy = LAM ? Qxy0 + slam * (sux * sdy + suy * sdx) : Qxy0;
     const S pxx_eq = (S)c.kappa * (sdx * sdx - sdy * sdy) + dQ;
     const S pxy_eq = (S)c.kappa * sdx * sdy + Qxy;
     const R uF = ux * F;
@@ -506,7 +509,7 @@ __device__ __forceinline__ void step_tile_bin(const StepArgs& a, int tile, R* ld
     const R nu = nu_g + R(0.5) * (pc + R(1)) * (nu_l - nu_g);
     const R omega = R(2) / (R(6) * nu + R(1));
     R o[9];
-    collide(c, m, rho, ux, uy, dX, R(0), omega, dxq, dyq, F, o);
+    collide<R, R, false>(c, m, rho, ux, uy, dX, R(0), omega, dxq, dyq, F, o);
     float* __restrict__ fdst = k.dst + c.off_f;
     const long long own_idx = (long long)yw * g.pitch + xw;
 #pragma unroll

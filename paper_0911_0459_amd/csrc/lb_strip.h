@@ -173,12 +173,13 @@ __device__ __forceinline__ void st(const Planes& q, float v, int voff, int soff)
 }
 
 // 1/x for a positive normal x in the collision's arithmetic type: in FP64 the
-// hardware FP32 reciprocal (1 ulp) refined by two Newton steps (relative error
-// at the FP64 rounding level), far fewer instructions and registers than the
-// correctly rounded division; in FP32 the division itself.
+// hardware FP32 reciprocal (relative error below 2^-22 after the rounding of x
+// to FP32) refined by one Newton step, which squares the relative error (below
+// 1e-13: far below the FP32 rounding of the stored state), with far fewer
+// instructions and registers than the correctly rounded division; in FP32 the
+// division itself.
 __device__ __forceinline__ double recip(double x) {
-    double r = (double)__builtin_amdgcn_rcpf((float)x);
-    r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+    const double r = (double)__builtin_amdgcn_rcpf((float)x);
     return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 }
 
@@ -219,6 +220,48 @@ __device__ __forceinline__ void pull_lane(const Planes& q, const LaneCols& L, co
     f[6] = get(6, L.bp, sp);
     f[7] = get(7, L.bp, sm_);
     f[8] = get(8, L.bm, sp);
+}
+
+// phi(t+1) - phi(t) at a node (binary model), shared by the row-sweep kernels so
+// that both compile the same arithmetic.  phi, ux, uy, am: the node's order
+// parameter, velocity and direction-free part A = Gamma mu - phi |u|^2 / 2;
+// src(i, a, p, x, y) fetches A, phi, ux, uy of the source node r - e_i.
+//   phi(t+1) = phi(t) + sum_i g^eq_i(source of i) - sum_i g^eq_i(r), i >= 1.
+// With g^eq_i = w_i (A + phi e_i.u (1 + 3/2 e_i.u)), sum_i w_i = 5/3 and
+// sum_i w_i (e_i.u)^2 = |u|^2 (Appendix A moments), this is
+//   sum_i w_i [(A_src - A) + phi_src e_i.u_src (1 + 3/2 e_i.u_src)] - 3/2 phi |u|^2.
+// Writing the A part as differences makes the update of a uniform region
+// exactly zero; a closed-form sum_i w_i A would not round like the eight
+// incoming terms, and the same small excess at every bulk node would drift the
+// total phi steadily.  A solid source contributes the bounce-back of
+// g*_opp(i)(r) (no A difference); its source entries are fetched but unused.
+template <typename Src>
+__device__ __forceinline__ float phi_delta(unsigned sm, float phi, float ux, float uy, float am, Src src) {
+    auto adv = [](int i, float pp, float ax, float ay) {
+        const float eu = (float)ex_(i) * ax + (float)ey_(i) * ay;
+        return pp * eu * (1.f + 1.5f * eu);
+    };
+    auto incoming = [&](int i) {
+        float a, p, x, y;
+        src(i, a, p, x, y);
+        return (a - am) + adv(i, p, x, y);
+    };
+    float sa = 0.f, sd = 0.f;   // axis and diagonal sums
+    if (sm == 0u) {   // no solid neighbour: every source streams
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            if (i <= 4) sa += incoming(i);
+            else sd += incoming(i);
+        }
+    } else {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const float t = ((sm >> opp_(i)) & 1u) ? adv(opp_(i), phi, ux, uy) : incoming(i);
+            if (i <= 4) sa += t;
+            else sd += t;
+        }
+    }
+    return (sa * (1.f / 3.f) + sd * (1.f / 12.f)) - 1.5f * phi * (ux * ux + uy * uy);
 }
 
 // ---- binary model --------------------------------------------------------------
@@ -387,41 +430,22 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
             const float nu = c.nu_g + 0.5f * (pc + 1.f) * (c.nu_l - c.nu_g);
             const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
             CT o[9];
-            collide<CT, ST>(c, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            collide<CT, ST, false>(c, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
             // the phi update below is not to be interleaved with the collision
             // (its LDS reads would be hoisted into the collision's register peak)
             __builtin_amdgcn_sched_barrier(0);
-            // phi(t+1) = phi(t) + sum_i g^eq_i(source of i) - sum_i g^eq_i(r), i >= 1.
-            // With g^eq_i = w_i (A + phi e_i.u (1 + 3/2 e_i.u)), A = Gamma mu - phi |u|^2 / 2,
-            // sum_i w_i = 5/3 and sum_i w_i (e_i.u)^2 = |u|^2 (Appendix A moments), this is
-            //   sum_i w_i [(A_src - A) + phi_src e_i.u_src (1 + 3/2 e_i.u_src)] - 3/2 phi |u|^2.
-            // Writing the A part as differences makes the update of a uniform region
-            // exactly zero; a closed-form sum_i w_i A would not round like the eight
-            // incoming terms, and the same small excess at every bulk node would
-            // drift the total phi steadily.
             const float uxf = UX[r3(0)][k], uyf = UY[r3(0)][k];
-            const float am = AM[r3(0)][k];
-            auto adv = [&](int i, float pp, float ax, float ay) {
-                const float eu = (float)ex_(i) * ax + (float)ey_(i) * ay;
-                return pp * eu * (1.f + 1.5f * eu);
-            };
-            float sa = 0.f, sd = 0.f;   // axis and diagonal sums
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                float t;
-                if ((sm_cur >> opp_(i)) & 1u) {
-                    t = adv(opp_(i), phi, uxf, uyf);   // bounce-back of g*_opp(i)(r): no A difference
-                } else {
-                    const int s3 = r3(-ey_(i)), s5 = r5(-ey_(i)), sk = k - ex_(i);
-                    t = (AM[s3][sk] - am) + adv(i, PH[s5][sk + 1], UX[s3][sk], UY[s3][sk]);
-                }
-                if (i <= 4) sa += t;
-                else sd += t;
-            }
-            const float dphi = (sa * (1.f / 3.f) + sd * (1.f / 12.f)) - 1.5f * phi * (uxf * uxf + uyf * uyf);
+            const float dphi = phi_delta(sm_cur, phi, uxf, uyf, AM[r3(0)][k],
+                                         [&](int i, float& a, float& p, float& x, float& y) {
+                                             const int s3 = r3(-ey_(i)), sk = k - ex_(i);
+                                             a = AM[s3][sk];
+                                             p = PH[r5(-ey_(i))][sk + 1];
+                                             x = UX[s3][sk];
+                                             y = UY[s3][sk];
+                                         });
             st(pd, phi + dphi, L.b0, srow);
         }
         // (e) rotate the row state

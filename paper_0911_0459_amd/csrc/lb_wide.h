@@ -42,8 +42,9 @@ __device__ __forceinline__ void lds_barrier() {
 // Role of a thread of a wide strip.
 struct WideLane {
     int dx;     // its column minus xs (wrapped periodically by lane_cols)
-    int uj;     // index of its column in a u / mu row (0 for lanes that compute none)
-    int pj;     // index of its column in a phi row
+    int uj;     // index of its column in a row of columns xs-1.. (0 for lanes that compute no u)
+    int pj;     // index of its column in a row of columns xs-2..
+    int qj;     // pj for lanes that compute u, else 2 (a safe index for their unused stencils)
     bool main;  // a main wavefront lane: one output column
     bool um;    // computes u and mu (main lanes; halo lanes 0 and 1)
     bool ph;    // stores phi (main lanes; halo lanes 0..3)
@@ -63,14 +64,16 @@ __device__ __forceinline__ WideLane wide_lane() {
     }
     r.uj = r.um ? r.dx + 1 : 0;
     r.pj = r.dx + 2;
+    r.qj = r.um ? r.pj : 2;
     return r;
 }
 
 // ---- binary model --------------------------------------------------------------
 // Reads f*(t-1) and phi(t) of one wide strip chunk, writes f*(t) and phi(t+1).
-// (at most 80 vector registers: six wavefronts per SIMD, six workgroups per CU)
+// (at most 72 vector registers and 19 KB of LDS: seven wavefronts per SIMD,
+// seven workgroups per CU)
 template <typename MT, typename CT, typename ST = CT>
-__global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
+__global__ void __launch_bounds__(WIDE_THREADS, 7) lb_wide_bin(StripArgs a) {
     const int si = strip_index(a);
     if (si < 0) return;
     const StripDev s = a.strips[si];
@@ -83,32 +86,38 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     const Planes fd = planes_of((sb ? a.arena0 : a.arena1) + c.off_f, 9, P, c.pitch);
     const Planes pd = planes_of((sb ? a.arena0 : a.arena1) + c.off_phi, 1, P, c.pitch);
 
-    // ring slots: row y of the phi ring is y mod 8, of the u / mu rings y mod 4.
-    // No barrier ends a row: a wavefront that has passed row y's second barrier
-    // and starts row y+1 writes phi row y+3 (slot y-5 mod 8) and u row y+2 (slot
-    // y-2 mod 4), while a slower one may still be in row y's last phase reading
-    // phi, u and mu rows y-1..y+1; and it waits at row y+1's first barrier
-    // before it writes mu row y+2, which row y's last phase no longer reads.
-    __shared__ float PH[8][WP];
-    // velocity and Gamma mu - phi |u|^2 / 2, the part of g^eq that does not
-    // depend on the direction
-    __shared__ float UX[4][WU], UY[4][WU], AM[4][WU];
+    // One LDS ring of RING rows, each slot holding the row's phi, ux, uy and
+    // A = Gamma mu - phi |u|^2 / 2 (the part of g^eq that does not depend on the
+    // direction) over the columns xs-2 .. xs+WIDE_OUT+1: one address register
+    // serves all four, at immediate offsets.  Row y+d of the row being finished,
+    // y, is in slot sl(d).  No barrier ends a row: a wavefront that has passed
+    // row y's second barrier and starts row y+1 writes phi row y+3 and u row y+2
+    // (slots 4 and 3 rows on from y-1 in a ring of 6), while a slower one may
+    // still be in row y's last phase reading rows y-1..y+1; and it waits at row
+    // y+1's first barrier before it writes A of row y+2.
+    enum { R_PH = 0, R_UX = 1, R_UY = 2, R_AM = 3, RING = 6 };
+    __shared__ float RG[RING][4][WP];
 
     const WideLane W = wide_lane();
     const int xl = s.xs + W.dx;
     const LaneCols L = lane_cols(g, xl);
     const bool out_col = W.main && xl < g.nx;
-    const int uj = W.uj, pj = W.pj;
+    const int pj = W.pj, qj = W.qj;
     const float G2 = 2.f * c.G;
     const float kap = c.kappa, Gam = c.Gamma;
-    auto s8 = [](int y) { return y & 7; };   // y >= -2: rows are offset by 8 below
-    auto s4 = [](int y) { return y & 3; };
+    int ry = 2;   // slot of the row being finished (the chunk's first row to begin with)
+    auto sl = [&](int d) {   // slot of that row + d, -2 <= d <= 3
+        int v = ry + d;
+        v += v < 0 ? RING : 0;
+        v -= v >= RING ? RING : 0;
+        return v;
+    };
 
     // phi is loaded unconditionally (solid nodes have valid addresses) and
     // masked when stored, so that no instruction waits on it early
     auto phi_load = [&](const RowInfo& r) { return ld(ps, L.b0, r.y0 * ps.rb); };
     auto phi_store = [&](int sl, const RowInfo& r, float m) {
-        if (W.ph) PH[sl][pj] = (L.t0 && r.w0) ? 0.f : m;
+        if (W.ph) RG[sl][R_PH][pj] = (L.t0 && r.w0) ? 0.f : m;
     };
     // moments of a pulled row (FP32, kept by the caller) and its velocity into LDS
     auto u_row = [&](int sl, const float (&f)[9], bool fluid, unsigned sm, Mom<float>& m) {
@@ -124,30 +133,28 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             m = Mom<float>{0.f, 0.f, 0.f, 0.f, 0.f};
         }
         if (W.um) {
-            UX[sl][uj] = ux;
-            UY[sl][uj] = uy;
+            RG[sl][R_UX][qj] = ux;
+            RG[sl][R_UY][qj] = uy;
         }
     };
-    // stencils of phi (rows pm, p0, pp), Gamma mu and the direction-free part of g^eq
-    auto mu_row = [&](int sl, int pm, int p0, int pp, bool fluid, unsigned sm, float& dx, float& dy, float& lap) {
+    // stencils of phi (rows sm1, sl, sp1), Gamma mu and A of row slot sl
+    auto mu_row = [&](int sm1, int sl, int sp1, bool fluid, unsigned sm, float& dx, float& dy, float& lap) {
         float v = 0.f;
         dx = dy = lap = 0.f;
         if (fluid) {
-            stencil3(PH[pm], PH[p0], PH[pp], uj + 1, sm, G2, dx, dy, lap);
-            const float ph = PH[p0][uj + 1];
+            stencil3(RG[sm1][R_PH], RG[sl][R_PH], RG[sp1][R_PH], qj, sm, G2, dx, dy, lap);
+            const float ph = RG[sl][R_PH][qj];
             const float gmu = Gam * (mu_bulk(c, ph) - kap * lap);
-            const float ux = UX[sl][uj], uy = UY[sl][uj];
+            const float ux = RG[sl][R_UX][qj], uy = RG[sl][R_UY][qj];
             v = gmu - 0.5f * ph * (ux * ux + uy * uy);
         }
-        if (W.um) AM[sl][uj] = v;
+        if (W.um) RG[sl][R_AM][qj] = v;
     };
 
-    // rows are addressed in the rings as y + 8 (y >= ya - 2 >= -2)
-    const int yo = 8;
     // ---- prologue: phi rows ya-2..ya+1; u, mu of rows ya-1, ya
     for (int d = -2; d <= 1; ++d) {
         const RowInfo rr = row_info(g, s.ya + d);
-        phi_store(s8(s.ya + d + yo), rr, phi_load(rr));
+        phi_store(sl(d), rr, phi_load(rr));
     }
     float f[9];
     Mom<float> mom_cur;
@@ -155,17 +162,16 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     unsigned sm = solid_bits(L, ri);
     bool fl = !(L.t0 && ri.w0);
     pull_lane(fs, L, ri, sm, f);
-    u_row(s4(s.ya - 1 + yo), f, fl, sm, mom_cur);
+    u_row(sl(-1), f, fl, sm, mom_cur);
     ri = row_info(g, s.ya);
     unsigned sm_cur = solid_bits(L, ri);
     bool fl_cur = !(L.t0 && ri.w0);
     pull_lane(fs, L, ri, sm_cur, f);
-    u_row(s4(s.ya + yo), f, fl_cur, sm_cur, mom_cur);
+    u_row(sl(0), f, fl_cur, sm_cur, mom_cur);
     lds_barrier();
     float dx_cur, dy_cur, lap_cur, t0, t1, t2;
-    mu_row(s4(s.ya - 1 + yo), s8(s.ya - 2 + yo), s8(s.ya - 1 + yo), s8(s.ya + yo), fl, sm, t0, t1, t2);
-    mu_row(s4(s.ya + yo), s8(s.ya - 1 + yo), s8(s.ya + yo), s8(s.ya + 1 + yo), fl_cur, sm_cur, dx_cur, dy_cur,
-           lap_cur);
+    mu_row(sl(-2), sl(-1), sl(0), fl, sm, t0, t1, t2);
+    mu_row(sl(-1), sl(0), sl(1), fl_cur, sm_cur, dx_cur, dy_cur, lap_cur);
     // Requests run one row ahead of the arithmetic; the two request buffers swap
     // roles every row (the loop is unrolled by two), so a finished request is
     // never copied: a copy would wait for every load in flight.
@@ -188,7 +194,6 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
 
     // one row y: n holds the requests for row y+1, p receives those for row y+2
     auto iter = [&](int y, Ahead& n, Ahead& p) {
-        const int yr = y + yo;
         // (a) requests for the next row: row y+2 pulled, phi row y+3 (in the last
         // row of the chunk a repeat of the previous requests: cache hits, unused)
         const int ya2 = y + 1 < s.yb ? y + 2 : y + 1;
@@ -200,13 +205,13 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
         p.pm = phi_load(p.rph);
         __builtin_amdgcn_sched_barrier(0);
         // (b) phi row y+2; u and moments of row y+1
-        phi_store(s8(yr + 2), n.rph, n.pm);
+        phi_store(sl(2), n.rph, n.pm);
         Mom<float> mom_n;
-        u_row(s4(yr + 1), n.f, n.fl, n.sm, mom_n);
+        u_row(sl(1), n.f, n.fl, n.sm, mom_n);
         lds_barrier();
         // (c) stencils and mu of row y+1
         float dx_n, dy_n, lap_n;
-        mu_row(s4(yr + 1), s8(yr), s8(yr + 1), s8(yr + 2), n.fl, n.sm, dx_n, dy_n, lap_n);
+        mu_row(sl(0), sl(1), sl(2), n.fl, n.sm, dx_n, dy_n, lap_n);
         lds_barrier();
         // (d) collision and phi update of row y (main lanes)
         if (out_col && fl_cur) {
@@ -217,8 +222,8 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             uniform_opaque(cd.rho_ref);
             uniform_opaque(cd.phib);
             uniform_opaque(cd.B);
-            const int p0 = s8(yr), u0 = s4(yr);
-            const float phi = PH[p0][pj];
+            const int s0 = sl(0);
+            const float phi = RG[s0][R_PH][pj];
             const Mom<CT> mc{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
             const CT F_cur = sm_cur ? CT(0) : (CT)cd.Fx;
             const CT rho_c = (CT)cd.rho_ref + mc.drho;
@@ -234,37 +239,23 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             const float nu = cd.nu_g + 0.5f * (pc + 1.f) * (cd.nu_l - cd.nu_g);
             const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
             CT o[9];
-            collide<CT, ST>(cd, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            collide<CT, ST, false>(cd, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
             // the phi update below is not to be interleaved with the collision
             // (its LDS reads would be hoisted into the collision's register peak)
             __builtin_amdgcn_sched_barrier(0);
-            // phi(t+1) = phi(t) + sum_i [g^eq_i(r - e_i) - g^eq_i(r)], i >= 1, with the
-            // direction-free part A = Gamma mu - phi |u|^2 / 2 taken as differences
-            // (exactly zero in a uniform region), as in lb_strip_bin
-            const float uxf = UX[u0][uj], uyf = UY[u0][uj];
-            const float am = AM[u0][uj];
-            auto adv = [&](int i, float pp, float ax, float ay) {
-                const float eu = (float)ex_(i) * ax + (float)ey_(i) * ay;
-                return pp * eu * (1.f + 1.5f * eu);
-            };
-            float sa = 0.f, sd = 0.f;   // axis and diagonal sums
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
-                float t;
-                if ((sm_cur >> opp_(i)) & 1u) {
-                    t = adv(opp_(i), phi, uxf, uyf);   // bounce-back of g*_opp(i)(r): no A difference
-                } else {
-                    const int su = s4(yr - ey_(i)), sp = s8(yr - ey_(i));
-                    const int ku = uj - ex_(i), kp = pj - ex_(i);
-                    t = (AM[su][ku] - am) + adv(i, PH[sp][kp], UX[su][ku], UY[su][ku]);
-                }
-                if (i <= 4) sa += t;
-                else sd += t;
-            }
-            const float dphi = (sa * (1.f / 3.f) + sd * (1.f / 12.f)) - 1.5f * phi * (uxf * uxf + uyf * uyf);
+            // phi(t+1) (phi_delta, as in lb_strip_bin)
+            const float uxf = RG[s0][R_UX][pj], uyf = RG[s0][R_UY][pj];
+            const float dphi = phi_delta(sm_cur, phi, uxf, uyf, RG[s0][R_AM][pj],
+                                         [&](int i, float& a, float& p, float& x, float& y) {
+                                             const int sn = sl(-ey_(i)), kn = pj - ex_(i);
+                                             a = RG[sn][R_AM][kn];
+                                             p = RG[sn][R_PH][kn];
+                                             x = RG[sn][R_UX][kn];
+                                             y = RG[sn][R_UY][kn];
+                                         });
             st(pd, phi + dphi, L.b0, srow);
         }
         // (e) rotate the row state
@@ -274,6 +265,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
         dx_cur = dx_n;
         dy_cur = dy_n;
         lap_cur = lap_n;
+        ry = ry == RING - 1 ? 0 : ry + 1;
     };
     for (int y = s.ya; y < s.yb; y += 2) {
         iter(y, A, B);
