@@ -70,10 +70,11 @@ __device__ __forceinline__ WideLane wide_lane() {
 
 // ---- binary model --------------------------------------------------------------
 // Reads f*(t-1) and phi(t) of one wide strip chunk, writes f*(t) and phi(t+1).
-// (at most 72 vector registers and 19 KB of LDS: seven wavefronts per SIMD,
-// seven workgroups per CU)
+// (at most 80 vector registers and 19 KB of LDS: six wavefronts per SIMD, six
+// workgroups per CU; seven fit, but evict more of the halo lines that
+// neighbouring strips share and measured slower)
 template <typename MT, typename CT, typename ST = CT>
-__global__ void __launch_bounds__(WIDE_THREADS, 7) lb_wide_bin(StripArgs a) {
+__global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     const int si = strip_index(a);
     if (si < 0) return;
     const StripDev s = a.strips[si];
