@@ -97,10 +97,8 @@ def copy_bandwidth(L, reps: int = 20, nbytes: int = 1 << 31):
     return {"bytes_per_copy": 2 * nbytes, "us_per_copy": round(us, 1), "gbps": round(2 * nbytes / us / 1e3, 1)}
 
 
-def cpu_baseline(w, target_s: float = 15.0):
-    """The FP64 oracle on one capillary of the workload, for a bounded number
-    of steps (calibrated to about target_s seconds)."""
-    import oracle
+def make_oracle(w):
+    """The FP64 oracle set up on workload w (the timing legs only)."""
     from oracle import Oracle, OracleGeom, OracleParams
     from oracle import physics as P
     G = w.wall_grad if w.wall_grad is not None else (
@@ -108,7 +106,14 @@ def cpu_baseline(w, target_s: float = 15.0):
         else P.vdw_wall_gradient(w.theta_deg, w.kappa, w.a, w.b, w.T))
     p = OracleParams(model=w.model, kappa=w.kappa, a=w.a, b=w.b, T=w.T, A=w.A, B=w.B, Gamma=w.Gamma,
                      nu_l=w.nu_l, nu_g=w.nu_g, wall_grad=G)
-    o = Oracle(p, OracleGeom(**w.geom.asdict()), w.initial_field())
+    return Oracle(p, OracleGeom(**w.geom.asdict()), w.initial_field())
+
+
+def cpu_baseline(w, target_s: float = 15.0):
+    """The FP64 oracle on one capillary of the workload, for a bounded number
+    of steps (calibrated to about target_s seconds)."""
+    import oracle
+    o = make_oracle(w)
     fluid = w.geom.fluid_count()
     t0 = time.perf_counter()
     o.step(5)
@@ -120,6 +125,46 @@ def cpu_baseline(w, target_s: float = 15.0):
     return {"value": fluid * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"capillary {w.name} ({w.geom.nx}x{w.geom.ny}, {fluid} fluid nodes), "
                       f"{n} steps, {dt:.1f} s"}
+
+
+def oracle_next_to_gpu(L, log):
+    """The FP64 oracle and the GPU on the three single-lattice configurations:
+    vdW 256x64 for 2000 steps, binary 1024x128 for 10^4 steps and binary
+    4096x256 for 2000 steps (its 2*10^5-step run extrapolated linearly)."""
+    import oracle
+    import torch
+    from paper_0911_0459_amd import inputs as I
+    cases = [("vdw_256x64", I.vdw_capillary_256x64(), 2000, 2000),
+             ("binary_1024x128", I.binary_capillary_1024x128(), 10_000, 10_000),
+             ("binary_4096x256", I.binary_capillary_4096x256(), 2000, 200_000)]
+    out = []
+    for name, w, n, full in cases:
+        fluid = w.geom.fluid_count()
+        o = make_oracle(w)
+        t0 = time.perf_counter()
+        for k in range(0, n, 500):
+            o.step(min(500, n - k))
+            log(f"oracle {name}: {k + min(500, n - k)} of {n} steps, {time.perf_counter() - t0:.0f} s")
+        t_cpu = time.perf_counter() - t0
+        lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), w.initial_field())
+        lat.autotune(trial_steps=10)
+        lat.step(50)
+        lat.check()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(n)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t0
+        lat.check()
+        launch = lat.launch_config().asdict()
+        lat.close()
+        out.append({"config": name, "fluid_nodes": fluid, "steps": n,
+                    "oracle_mlups": round(fluid * n / t_cpu / 1e6, 2), "oracle_s": round(t_cpu, 1),
+                    "oracle_full_run_s": round(t_cpu * full / n, 1),
+                    "gpu_mlups": round(fluid * n / t_gpu / 1e6, 1), "gpu_s": round(t_gpu, 4),
+                    "gpu_launch": launch, "full_run_steps": full})
+        log(f"{name}: oracle {out[-1]['oracle_mlups']} MLUPS, GPU {out[-1]['gpu_mlups']} MLUPS")
+    return {"oracle_threads": oracle.threads(), "configs": out}
 
 
 def sweep_compare(works, log):
@@ -177,6 +222,8 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=-1, help="steps per HIP graph (0: direct launches)")
     ap.add_argument("--copy-probe", action="store_true", help="time the plain copy kernel only")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep wall-time comparison")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="time the FP64 oracle next to the GPU on the three single-lattice configurations only")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
@@ -191,6 +238,10 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         print(json.dumps({"copy_probe": copy_bandwidth(L, args.steps)}))
+        return
+    if args.oracle_timing:
+        log = lambda m: print(m, file=sys.stderr, flush=True)
+        print(json.dumps({"oracle_next_to_gpu": oracle_next_to_gpu(L, log)}))
         return
     works, config = build_workload(args.workload)
     model = works[0].model
