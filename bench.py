@@ -73,6 +73,14 @@ def build_workload(name: str):
     if name == "vdw4096":
         w = I.vdw_capillary_4096x256()
         return [w], {"workload": "vdw_4096x256_60deg", "lattice": "4096x256", "tube_h": 100, "tube_len": 3072}
+    if name == "vdw16k":
+        w = I.vdw_capillary_16384x1024()
+        return [w], {"workload": "vdw_16384x1024_60deg", "lattice": "16384x1024", "tube_h": 400,
+                     "tube_len": 12288}
+    if name == "single16k":
+        w = I.binary_capillary_16384x1024()
+        return [w], {"workload": "binary_16384x1024_ratio10_60deg", "lattice": "16384x1024", "tube_h": 400,
+                     "tube_len": 12288}
     if name == "single1024":
         w = I.binary_capillary_1024x128()
         return [w], {"workload": "binary_1024x128_ratio10_60deg", "lattice": "1024x128", "tube_h": 40,
@@ -212,7 +220,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="sweep", choices=["sweep", "single4096", "single1024", "vdw4096"])
+    ap.add_argument("--workload", default="sweep",
+                    choices=["sweep", "single4096", "single1024", "vdw4096", "vdw16k", "single16k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile-rows", type=int, default=0, help="pin the launch shape (with --schedule)")

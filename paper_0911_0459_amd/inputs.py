@@ -150,6 +150,25 @@ def vdw_capillary_4096x256(seed: int = 9) -> Workload:
                     liquid=4.54, gas=2.59, **VDW_CONSTS)
 
 
+def vdw_capillary_16384x1024(seed: int = 10) -> Workload:
+    """The liquid-gas model on a lattice far larger than the last-level cache:
+    16384x1024 (9.1 M fluid nodes), tube H=400 and length 12288, the C1
+    constants (nu = 0.1, -0.144)."""
+    g = Geometry(nx=16384, ny=1024, x_in=4096, tube_len=12288, tube_h=400, y0=312)
+    return Workload("vdw_16384x1024", "vdw", g, steps=200_000, sample_every=2000, seed=seed,
+                    nu_l=0.1, nu_g=0.1, theta_deg=60.0, wall_grad=-0.144,
+                    liquid=4.54, gas=2.59, **VDW_CONSTS)
+
+
+def binary_capillary_16384x1024(seed: int = 11, ratio: float = 10.0) -> Workload:
+    """One binary capillary far larger than the last-level cache: 16384x1024
+    (9.1 M fluid nodes), tube H=400 and length 12288, ratio 10, 60 degrees."""
+    g = Geometry(nx=16384, ny=1024, x_in=4096, tube_len=12288, tube_h=400, y0=312)
+    nl, ng = viscosity_pair(ratio)
+    return Workload("binary_16384x1024", "binary", g, steps=200_000, sample_every=2000, seed=seed,
+                    nu_l=nl, nu_g=ng, theta_deg=60.0, liquid=1.0, gas=-1.0, **BIN_CONSTS)
+
+
 def binary_capillary_1024x128(seed: int = 2, ratio: float = 10.0) -> Workload:
     """Binary, 1024x128, tube H=40 and length 768, reservoir 256 wide,
     viscosity ratio 10, 60 degrees, 50k steps."""
