@@ -88,6 +88,7 @@ SHAPES = [
     dict(schedule=4, chunk_rows=0, graph_steps=64, fp64_arith=1),
     dict(schedule=4, chunk_rows=8, graph_steps=0, fp64_arith=0),
     dict(schedule=4, chunk_rows=5, graph_steps=2, fp64_arith=1),
+    dict(schedule=4, chunk_rows=16, graph_steps=64, fp64_arith=1),   # long chunks end in short tails
 ]
 
 
