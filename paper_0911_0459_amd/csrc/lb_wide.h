@@ -117,11 +117,11 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     // phi is loaded unconditionally (solid nodes have valid addresses) and
     // masked when stored, so that no instruction waits on it early
     auto phi_load = [&](const RowInfo& r) { return ld(ps, L.b0, r.y0 * ps.rb); };
-    auto phi_store = [&](int sl, const RowInfo& r, float m) {
-        if (W.ph) RG[sl][R_PH][pj] = (L.t0 && r.w0) ? 0.f : m;
+    auto phi_store = [&](int slot, const RowInfo& r, float m) {
+        if (W.ph) RG[slot][R_PH][pj] = (L.t0 && r.w0) ? 0.f : m;
     };
     // moments of a pulled row (FP32, kept by the caller) and its velocity into LDS
-    auto u_row = [&](int sl, const float (&f)[9], bool fluid, unsigned sm, Mom<float>& m) {
+    auto u_row = [&](int slot, const float (&f)[9], bool fluid, unsigned sm, Mom<float>& m) {
         float ux = 0.f, uy = 0.f;
         if (fluid) {
             const bool bnd = sm != 0u;
@@ -134,22 +134,22 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             m = Mom<float>{0.f, 0.f, 0.f, 0.f, 0.f};
         }
         if (W.um) {
-            RG[sl][R_UX][qj] = ux;
-            RG[sl][R_UY][qj] = uy;
+            RG[slot][R_UX][qj] = ux;
+            RG[slot][R_UY][qj] = uy;
         }
     };
-    // stencils of phi (rows sm1, sl, sp1), Gamma mu and A of row slot sl
-    auto mu_row = [&](int sm1, int sl, int sp1, bool fluid, unsigned sm, float& dx, float& dy, float& lap) {
+    // stencils of phi (row slots below, at, above), Gamma mu and A of the row at slot `at`
+    auto mu_row = [&](int below, int at, int above, bool fluid, unsigned sm, float& dx, float& dy, float& lap) {
         float v = 0.f;
         dx = dy = lap = 0.f;
         if (fluid) {
-            stencil3(RG[sm1][R_PH], RG[sl][R_PH], RG[sp1][R_PH], qj, sm, G2, dx, dy, lap);
-            const float ph = RG[sl][R_PH][qj];
+            stencil3(RG[below][R_PH], RG[at][R_PH], RG[above][R_PH], qj, sm, G2, dx, dy, lap);
+            const float ph = RG[at][R_PH][qj];
             const float gmu = Gam * (mu_bulk(c, ph) - kap * lap);
-            const float ux = RG[sl][R_UX][qj], uy = RG[sl][R_UY][qj];
+            const float ux = RG[at][R_UX][qj], uy = RG[at][R_UY][qj];
             v = gmu - 0.5f * ph * (ux * ux + uy * uy);
         }
-        if (W.um) RG[sl][R_AM][qj] = v;
+        if (W.um) RG[at][R_AM][qj] = v;
     };
 
     // ---- prologue: phi rows ya-2..ya+1; u, mu of rows ya-1, ya
