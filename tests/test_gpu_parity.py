@@ -133,6 +133,30 @@ def test_wide_strips_across_strip_boundaries(L, model):
     assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (drho, dphi, du)
 
 
+@pytest.mark.parametrize("cfg", [dict(schedule=4, chunk_rows=0), dict(schedule=4, chunk_rows=4),
+                                 dict(schedule=3, chunk_rows=0), dict(tile_rows=2, schedule=1)],
+                         ids=["wide", "wide-ch4", "strip", "tile"])
+@pytest.mark.parametrize("model", ["vdw", "binary"])
+def test_smallest_lattice(L, model, cfg):
+    """5x3, fully periodic (the smallest lattice the library accepts is 3x3):
+    every row and column index of the sweeps wraps, and one strip covers the
+    lattice many times over."""
+    g = I.Geometry(nx=5, ny=3)
+    if model == "vdw":
+        w = I.Workload("vdw_5x3", "vdw", g, 0, 0, seed=41, nu_l=0.13, nu_g=0.13, wall_grad=0.0,
+                       liquid=4.5, gas=2.6, **I.VDW_CONSTS)
+        init = np.array([[4.5, 4.4, 3.0, 2.6, 2.7], [4.5, 4.2, 3.1, 2.6, 2.8], [4.3, 4.5, 2.9, 2.7, 2.6]])
+    else:
+        nl, ng = I.viscosity_pair(10.0)
+        w = I.Workload("bin_5x3", "binary", g, 0, 0, seed=42, nu_l=nl, nu_g=ng, wall_grad=0.0,
+                       liquid=1.0, gas=-1.0, **I.BIN_CONSTS)
+        init = np.array([[1.0, 0.8, -0.2, -1.0, -0.9], [0.9, 0.7, 0.1, -0.8, -1.0], [1.0, 0.6, -0.3, -0.9, -0.7]])
+    gpu, _ = gpu_run(L, w, 100, cfg=cfg, init=init)
+    orc, _ = run_oracle(w, 100, init=init)
+    drho, dphi, du = field_errors(w, gpu, orc)
+    assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (drho, dphi, du)
+
+
 def test_lambda_off_and_full_periodic_box(L):
     """No walls at all (tube_len 0) and the Galilean term switched off."""
     g = I.Geometry(nx=96, ny=40)
