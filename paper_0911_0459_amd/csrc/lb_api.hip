@@ -424,6 +424,7 @@ struct lb_ctx {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     long timed_steps = 0;
     int unstable = 0;
+    bool any_force = false;   // some capillary has a body force (row sweeps keep the forcing terms)
 };
 
 namespace {
@@ -495,20 +496,30 @@ int grid_of(const lb_ctx* c) {
 // its registers would allow.
 constexpr size_t STRIP_BIN_LDS_PAD = 6 * 1024;
 
-template <int MODEL, typename MT, typename CT, typename ST = CT>
-void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid) {
+template <int MODEL, typename MT, typename CT, typename ST, bool FORCE>
+void launch_strip_f(lb_ctx* c, const StripArgs& a, int grid) {
     const bool wide = c->cfg.schedule == 4;
     if constexpr (MODEL == 0) {
         if (wide)
-            hipLaunchKernelGGL((lb_wide_vdw<CT>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
+            hipLaunchKernelGGL((lb_wide_vdw<CT, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
         else
-            hipLaunchKernelGGL((lb_strip_vdw<CT>), dim3(grid), dim3(SW), 0, c->stream, a);
+            hipLaunchKernelGGL((lb_strip_vdw<CT, FORCE>), dim3(grid), dim3(SW), 0, c->stream, a);
     } else {
         if (wide)
-            hipLaunchKernelGGL((lb_wide_bin<MT, CT, ST>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
+            hipLaunchKernelGGL((lb_wide_bin<MT, CT, ST, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
         else
-            hipLaunchKernelGGL((lb_strip_bin<MT, CT, ST>), dim3(grid), dim3(SW), STRIP_BIN_LDS_PAD, c->stream, a);
+            hipLaunchKernelGGL((lb_strip_bin<MT, CT, ST, FORCE>), dim3(grid), dim3(SW), STRIP_BIN_LDS_PAD,
+                               c->stream, a);
     }
+}
+
+// without a body force anywhere in the batch the forcing terms are compiled out
+template <int MODEL, typename MT, typename CT, typename ST = CT>
+void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid) {
+    if (c->any_force)
+        launch_strip_f<MODEL, MT, CT, ST, true>(c, a, grid);
+    else
+        launch_strip_f<MODEL, MT, CT, ST, false>(c, a, grid);
 }
 
 // Enqueue one step (or the initialisation when init is true) from arena cur.
@@ -619,6 +630,7 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
         delete c;
         return s;
     }
+    for (const CapDev& d : c->L.caps) c->any_force = c->any_force || d.Fx != 0.f;
     // initial fields: finite, and inside the van der Waals range
     for (int k = 0; k < n; ++k) {
         if (!init_q[k]) {

@@ -207,8 +207,9 @@ __device__ __forceinline__ R mu_bulk(const CapDev& c, R phi) {
 //   dX:  X - X_ref, X = p0 - kappa q lap(q) the isotropic part of Eq. (equilibrium)
 //   lam: Galilean-term coefficient; dq: gradient of q; F: body force on this node
 // LAM = false drops the Galilean terms at compile time (lam must then be 0, as
-// in the binary model); the results are the same, with fewer instructions.
-template <typename R, typename S = R, bool LAM = true>
+// in the binary model) and FORCE = false the forcing terms (F must then be 0);
+// the results are the same, with fewer instructions.
+template <typename R, typename S = R, bool LAM = true, bool FORCE = true>
 __device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX, R lam, R omega,
                                         R dxq, R dyq, R F, R (&o)[9]) {
     const R kappa = (R)c.kappa;
@@ -225,12 +226,16 @@ __device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho,
     const R uF = ux * F;
     // common parts of the axis (b) and diagonal (d) populations minus their
     // reference values X_ref/3 and X_ref/12 (e, eps at equilibrium plus source)
-    const R b = dX * (R(1) / R(3)) + (trQ + kappa * grad2 + uF) * (R(1) / R(12));
-    const R d = dX * (R(1) / R(12)) + (trQ - R(0.5) * kappa * grad2 + uF) * (R(1) / R(12));
+    const R b = FORCE ? dX * (R(1) / R(3)) + (trQ + kappa * grad2 + uF) * (R(1) / R(12))
+                      : dX * (R(1) / R(3)) + (trQ + kappa * grad2) * (R(1) / R(12));
+    const R d = FORCE ? dX * (R(1) / R(12)) + (trQ - R(0.5) * kappa * grad2 + uF) * (R(1) / R(12))
+                      : dX * (R(1) / R(12)) + (trQ - R(0.5) * kappa * grad2) * (R(1) / R(12));
     const R hw = R(1) - R(0.5) * omega;
-    const R pxs = (R)((S)m.pxx - (S)omega * ((S)m.pxx - pxx_eq)) + hw * R(2) * uF;
-    const R pys = (R)((S)m.pxy - (S)omega * ((S)m.pxy - pxy_eq)) + hw * (uy * F);
-    const R jxs = m.jx + F, jys = m.jy;   // qx*, qy* = -jx*, -jy*
+    const R pxr = (R)((S)m.pxx - (S)omega * ((S)m.pxx - pxx_eq));
+    const R pyr = (R)((S)m.pxy - (S)omega * ((S)m.pxy - pxy_eq));
+    const R pxs = FORCE ? pxr + hw * R(2) * uF : pxr;
+    const R pys = FORCE ? pyr + hw * (uy * F) : pyr;
+    const R jxs = FORCE ? m.jx + F : m.jx, jys = m.jy;   // qx*, qy* = -jx*, -jy*
     const R a7 = R(0.25) * pxs, a8 = R(0.25) * pys;
     const R jx3 = jxs * (R(1) / R(3)), jy3 = jys * (R(1) / R(3));
     const R jpp = (jxs + jys) * (R(1) / R(12)), jpm = (jxs - jys) * (R(1) / R(12));

@@ -266,7 +266,7 @@ __device__ __forceinline__ float phi_delta(unsigned sm, float phi, float ux, flo
 
 // ---- binary model --------------------------------------------------------------
 // Reads f*(t-1) and phi(t) of one strip chunk, writes f*(t) and phi(t+1).
-template <typename MT, typename CT, typename ST = CT>
+template <typename MT, typename CT, typename ST = CT, bool FORCE = true>
 __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
     const int si = strip_index(a);
     if (si < 0) return;
@@ -415,10 +415,10 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
         if (out_col && fl_cur) {
             const float phi = PH[r5(0)][k + 1];
             const Mom<CT> mc{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
-            const CT F_cur = sm_cur ? CT(0) : (CT)c.Fx;
+            const CT F_cur = (FORCE && !sm_cur) ? (CT)c.Fx : CT(0);
             const CT rho_c = (CT)c.rho_ref + mc.drho;
             const CT inv_rho = recip(rho_c);
-            const CT ux_cur = (mc.jx + CT(0.5) * F_cur) * inv_rho, uy_cur = mc.jy * inv_rho;
+            const CT ux_cur = (FORCE ? mc.jx + CT(0.5) * F_cur : mc.jx) * inv_rho, uy_cur = mc.jy * inv_rho;
             const CT ph = (CT)phi, phib = (CT)c.phib;
             const CT dX = mc.drho * (CT(1) / CT(3)) +
                           CT(0.25) * (CT)c.B * ((ph - phib) * (ph + phib)) * (CT(3) * ph * ph + phib * phib) -
@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
             const float nu = c.nu_g + 0.5f * (pc + 1.f) * (c.nu_l - c.nu_g);
             const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
             CT o[9];
-            collide<CT, ST, false>(c, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            collide<CT, ST, false, FORCE>(c, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
@@ -468,7 +468,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
 }
 
 // ---- van der Waals model ---------------------------------------------------------
-template <typename CT>
+template <typename CT, bool FORCE = true>
 __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
     const int si = strip_index(a);
     if (si < 0) return;
@@ -535,7 +535,7 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
             uniform_opaque(cd.omega_l);
             stencil3(Q[r3(-1)], Q[r3(0)], Q[r3(1)], k, sm_cur, G2, dxf, dyf, lapf);
             const bool bnd = sm_cur != 0u;
-            const CT F = bnd ? CT(0) : (CT)cd.Fx;
+            const CT F = (FORCE && !bnd) ? (CT)cd.Fx : CT(0);
             CT fcur[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) fcur[i] = (CT)f[i];
@@ -543,7 +543,7 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
             const CT rho_ref = (CT)cd.rho_ref;
             const CT rho = rho_ref + m.drho;
             const CT inv_rho = recip(rho);
-            const CT ux = (m.jx + CT(0.5) * F) * inv_rho;
+            const CT ux = (FORCE ? m.jx + CT(0.5) * F : m.jx) * inv_rho;
             const CT uy = m.jy * inv_rho;
             const CT T = (CT)cd.T, av = (CT)cd.a;
             const CT ib = recip(CT(1) - (CT)cd.b * rho);
@@ -555,7 +555,7 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
                 lam = (recip(omega) - CT(0.5)) * (CT(1) / CT(3) - dp0);
             }
             CT o[9];
-            collide(cd, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
+            collide<CT, CT, true, FORCE>(cd, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);

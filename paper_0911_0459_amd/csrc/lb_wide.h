@@ -73,7 +73,7 @@ __device__ __forceinline__ WideLane wide_lane() {
 // (at most 80 vector registers and 19 KB of LDS: six wavefronts per SIMD, six
 // workgroups per CU; seven fit, but evict more of the halo lines that
 // neighbouring strips share and measured slower)
-template <typename MT, typename CT, typename ST = CT>
+template <typename MT, typename CT, typename ST = CT, bool FORCE = true>
 __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     const int si = strip_index(a);
     if (si < 0) return;
@@ -226,10 +226,10 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             const int s0 = sl(0);
             const float phi = RG[s0][R_PH][pj];
             const Mom<CT> mc{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
-            const CT F_cur = sm_cur ? CT(0) : (CT)cd.Fx;
+            const CT F_cur = (FORCE && !sm_cur) ? (CT)cd.Fx : CT(0);
             const CT rho_c = (CT)cd.rho_ref + mc.drho;
             const CT inv_rho = recip(rho_c);
-            const CT ux_cur = (mc.jx + CT(0.5) * F_cur) * inv_rho, uy_cur = mc.jy * inv_rho;
+            const CT ux_cur = (FORCE ? mc.jx + CT(0.5) * F_cur : mc.jx) * inv_rho, uy_cur = mc.jy * inv_rho;
             const CT ph = (CT)phi, phib = (CT)cd.phib;
             const CT dX = mc.drho * (CT(1) / CT(3)) +
                           CT(0.25) * (CT)cd.B * ((ph - phib) * (ph + phib)) * (CT(3) * ph * ph + phib * phib) -
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             const float nu = cd.nu_g + 0.5f * (pc + 1.f) * (cd.nu_l - cd.nu_g);
             const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
             CT o[9];
-            collide<CT, ST, false>(cd, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            collide<CT, ST, false, FORCE>(cd, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
 }
 
 // ---- van der Waals model ---------------------------------------------------------
-template <typename CT>
+template <typename CT, bool FORCE = true>
 __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
     const int si = strip_index(a);
     if (si < 0) return;
@@ -346,7 +346,7 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
             uniform_opaque(cd.omega_l);
             stencil3(Q[s4(yr - 1)], Q[s4(yr)], Q[s4(yr + 1)], uj, sm_cur, G2, dxf, dyf, lapf);
             const bool bnd = sm_cur != 0u;
-            const CT F = bnd ? CT(0) : (CT)cd.Fx;
+            const CT F = (FORCE && !bnd) ? (CT)cd.Fx : CT(0);
             CT fcur[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) fcur[i] = (CT)f[i];
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
             const CT rho_ref = (CT)cd.rho_ref;
             const CT rho = rho_ref + m.drho;
             const CT inv_rho = recip(rho);
-            const CT ux = (m.jx + CT(0.5) * F) * inv_rho;
+            const CT ux = (FORCE ? m.jx + CT(0.5) * F : m.jx) * inv_rho;
             const CT uy = m.jy * inv_rho;
             const CT T = (CT)cd.T, av = (CT)cd.a;
             const CT ib = recip(CT(1) - (CT)cd.b * rho);
@@ -366,7 +366,7 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
                 lam = (recip(omega) - CT(0.5)) * (CT(1) / CT(3) - dp0);
             }
             CT o[9];
-            collide(cd, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
+            collide<CT, CT, true, FORCE>(cd, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
