@@ -160,20 +160,28 @@ int count_tiles(const lb_geometry& g, int rows) {
 // section only covers the channel rows.  chunk = 0 keeps whole strips.
 constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
 constexpr size_t LB_STRIP_GROUP = 16;  // neighbouring strip columns listed chunk by chunk
+constexpr size_t LB_TAIL_COLS = 32;    // columns per XCD run whose last rows go to short chunks
 
 // Strip table of the row-sweep kernels.  Every strip column (width output
-// columns of one capillary, over the rows that hold fluid) is cut into chunks:
-// chunk rows each, except (for chunks of 16 rows or more) the last 2 * small
-// rows, which are cut into chunks of small = max(4, chunk / 4) rows.  The columns are dealt to the 8 XCDs in
-// contiguous runs of about equal row count; each XCD's run lists the long
-// chunks of its columns first and the short ones last, so the end of a step is
-// made of short strips (a small tail) while most rows go through long strips
-// (few prologues), and the chunks of one column share an L2.  Within a run,
-// groups of LB_STRIP_GROUP neighbouring columns are listed chunk by chunk
-// across the group, so that strips sharing halo columns run at the same time.
+// columns of one capillary, over the rows that hold fluid) is cut into
+// ceil(rows / chunk) chunks of balanced height (no short remainder chunk, whose
+// prologue would cost as much as a full chunk's).  The columns are dealt to the
+// 8 XCDs in contiguous runs of about equal row count.  For chunks of 16 rows or
+// more, the last 2 * small rows of the last LB_TAIL_COLS columns of each run
+// are cut into chunks of small = max(4, chunk / 4) rows and listed at the end
+// of the run, so that a step ends on short strips (a small tail) while most
+// rows go through long strips (few prologues, little re-read at chunk edges).
+// Within a run, groups of LB_STRIP_GROUP neighbouring columns are listed chunk
+// by chunk across the group, so that strips sharing halo columns run at the
+// same time, and the chunks of one column share an L2.
+// The kernels' row loops are unrolled (align = 2 binary, 3 vdW) so that request
+// buffers swap roles without copies, and the copies of a row's arithmetic may
+// round differently: every chunk starts a multiple of align rows after the
+// column's first row, so that each row is computed by the same copy whatever
+// the chunking, and the results do not depend on it.
 // xcd_start[x] .. xcd_start[x + 1] is XCD x's run.
 void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk, int width,
-                  std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
+                  int align, std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
     struct Col { int cap, xs, ya, yb; };
     std::vector<Col> cols;
     long long rows = 0;
@@ -189,8 +197,8 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
             rows += yb - ya;
         }
     }
-    // (chunks below 16 rows are short enough to end a step without a tail)
-    const int small = chunk < 16 ? chunk : std::max(LB_MIN_CHUNK, chunk / 4);
+    auto down = [&](int v) { return v - v % align; };
+    const int small = down(std::max(LB_MIN_CHUNK, chunk / 4) + align - 1);   // rounded up to align
     int n = 0;
     if (out) out->clear();
     std::vector<StripDev> tails;
@@ -202,7 +210,19 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
         tails.clear();
         const size_t c0 = ci;
         for (; ci < cols.size() && (done < goal || x == 7); ++ci) done += cols[ci].yb - cols[ci].ya;
-        // groups of LB_STRIP_GROUP neighbouring columns, chunk by chunk across the group
+        // (chunks below 16 rows are short enough to end a step without a tail)
+        const size_t tail_from = chunk < 16 ? ci : (ci - c0 > LB_TAIL_COLS ? ci - LB_TAIL_COLS : c0);
+        // rows of column j before its tail (a multiple of align when a tail follows)
+        auto body_of = [&](size_t j) {
+            const int r = cols[j].yb - cols[j].ya;
+            return j >= tail_from ? down(r - std::min(r, 2 * small)) : r;
+        };
+        auto chunks_of = [&](size_t j) { return (body_of(j) + chunk - 1) / chunk; };
+        // start of chunk k of column j, relative to its first row (k = chunks_of: the end)
+        auto start_of = [&](size_t j, int k) {
+            const int nb = chunks_of(j), body = body_of(j);
+            return k >= nb ? body : down((int)((long long)k * body / nb));
+        };
         for (size_t g0 = c0; g0 < ci; g0 += LB_STRIP_GROUP) {
             const size_t g1 = std::min(ci, g0 + LB_STRIP_GROUP);
             if (chunk <= 0) {
@@ -215,23 +235,21 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
             for (int k = 0;; ++k) {
                 bool any = false;
                 for (size_t j = g0; j < g1; ++j) {
-                    const Col& c = cols[j];
-                    const int tail = chunk < 16 ? 0 : std::min(c.yb - c.ya, 2 * small);
-                    const int y = c.ya + k * chunk;
-                    if (y >= c.yb - tail) continue;
+                    if (k >= chunks_of(j)) continue;
                     any = true;
-                    if (out) out->push_back(StripDev{c.cap, c.xs, y, std::min(y + chunk, c.yb - tail)});
+                    const int y0 = cols[j].ya + start_of(j, k), y1 = cols[j].ya + start_of(j, k + 1);
+                    if (y0 == y1) continue;   // (rounding to align emptied it)
+                    if (out) out->push_back(StripDev{cols[j].cap, cols[j].xs, y0, y1});
                     ++n;
                 }
                 if (!any) break;
             }
-            for (size_t j = g0; j < g1; ++j) {
-                const Col& c = cols[j];
-                const int tail = chunk < 16 ? 0 : std::min(c.yb - c.ya, 2 * small);
-                for (int y = c.yb - tail; y < c.yb; y += small) {
-                    tails.push_back(StripDev{c.cap, c.xs, y, std::min(y + small, c.yb)});
-                    ++n;
-                }
+        }
+        for (size_t j = tail_from; j < ci; ++j) {
+            const Col& c = cols[j];
+            for (int y = c.ya + body_of(j); y < c.yb; y += small) {
+                tails.push_back(StripDev{c.cap, c.xs, y, std::min(y + small, c.yb)});
+                ++n;
             }
         }
         if (out) out->insert(out->end(), tails.begin(), tails.end());
@@ -340,8 +358,8 @@ lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L
         std::vector<int> all(n, 1);
         // the finest chunking allowed, for either strip width
         int narrow = 0, wide = 0;
-        build_strips(gv, all, LB_MIN_CHUNK, STRIP_OUT, nullptr, &narrow);
-        build_strips(gv, all, LB_MIN_CHUNK, WIDE_OUT, nullptr, &wide);
+        build_strips(gv, all, LB_MIN_CHUNK, STRIP_OUT, 1, nullptr, &narrow);
+        build_strips(gv, all, LB_MIN_CHUNK, WIDE_OUT, 1, nullptr, &wide);
         L.max_strips = std::max(narrow, wide);
     }
     size_t o = 0;
@@ -450,7 +468,8 @@ lb_status upload_tiles(lb_ctx* c) {
         HIP_TRY(hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(), hipMemcpyHostToDevice,
                                c->stream));
     std::vector<StripDev> strips;
-    build_strips(c->G, c->active, c->cfg.chunk_rows, strip_width(c->cfg), &strips, nullptr, c->xcd_start);
+    build_strips(c->G, c->active, c->cfg.chunk_rows, strip_width(c->cfg), c->model == LB_BINARY ? 2 : 3, &strips,
+                 nullptr, c->xcd_start);
     if ((int)strips.size() > c->L.max_strips) return fail(LB_EINVAL, "strip table overflow");
     c->nstrips = (int)strips.size();
     if (!strips.empty())
