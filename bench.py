@@ -55,10 +55,12 @@ def traffic_from_profiles(kernel: str, workload: str, launch: dict):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    taken = d.get("launch", {})
-    if any(taken.get(k) != launch.get(k) for k in ("schedule", "chunk_rows", "fp64_arith", "tile_rows")):
-        return None
-    return d.get("hbm_bytes_per_launch")
+    keys = ("schedule", "chunk_rows", "fp64_arith", "tile_rows")
+    for entry in [d] + d.get("other_launches", []):
+        taken = entry.get("launch", {})
+        if all(taken.get(k) == launch.get(k) for k in keys):
+            return entry.get("hbm_bytes_per_launch")
+    return None
 
 
 def build_workload(name: str):
