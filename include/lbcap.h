@@ -237,8 +237,7 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *  tile_rows: rows per tile for schedules 0..2 (1, 2, 4 or 8).
  *  chunk_rows: target rows per strip chunk for schedules 3 and 4 (0, or 4..4096;
  *    default 8): each strip column is cut into chunks of about that height that
- *    start a multiple of 2 (binary) or 3 (vdW) rows apart, so that the results
- *    do not depend on it.
+ *    start an even number of rows apart, so that the results do not depend on it.
  *  graph_steps: steps captured per HIP graph (even, >= 2; 0 = no graphs).
  *  fp64_arith: 1 evaluates the collision in FP64 (schedules 3, 4; schedules 0..2
  *    then compute the whole step in FP64), 0 in FP32.  The stored state is FP32

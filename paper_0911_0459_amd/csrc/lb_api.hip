@@ -174,11 +174,11 @@ constexpr size_t LB_TAIL_COLS = 32;    // columns per XCD run whose last rows go
 // Within a run, groups of LB_STRIP_GROUP neighbouring columns are listed chunk
 // by chunk across the group, so that strips sharing halo columns run at the
 // same time, and the chunks of one column share an L2.
-// The kernels' row loops are unrolled (align = 2 binary, 3 vdW) so that request
-// buffers swap roles without copies, and the copies of a row's arithmetic may
-// round differently: every chunk starts a multiple of align rows after the
-// column's first row, so that each row is computed by the same copy whatever
-// the chunking, and the results do not depend on it.
+// The kernels' row loops are unrolled by align = 2 so that request buffers swap
+// roles without copies, and the copies of a row's arithmetic may round
+// differently: every chunk starts a multiple of align rows after the column's
+// first row, so that each row is computed by the same copy whatever the
+// chunking, and the results do not depend on it.
 // xcd_start[x] .. xcd_start[x + 1] is XCD x's run.
 void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk, int width,
                   int align, std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
@@ -468,8 +468,7 @@ lb_status upload_tiles(lb_ctx* c) {
         HIP_TRY(hipMemcpyAsync(c->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(), hipMemcpyHostToDevice,
                                c->stream));
     std::vector<StripDev> strips;
-    build_strips(c->G, c->active, c->cfg.chunk_rows, strip_width(c->cfg), c->model == LB_BINARY ? 2 : 3, &strips,
-                 nullptr, c->xcd_start);
+    build_strips(c->G, c->active, c->cfg.chunk_rows, strip_width(c->cfg), 2, &strips, nullptr, c->xcd_start);
     if ((int)strips.size() > c->L.max_strips) return fail(LB_EINVAL, "strip table overflow");
     c->nstrips = (int)strips.size();
     if (!strips.empty())

@@ -491,25 +491,34 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
     int p3 = 0;   // slot of row ya-1
     auto r3 = [&](int d) { int v = p3 + 1 + d; v -= v >= 3 ? 3 : 0; v -= v >= 3 ? 3 : 0; return v; };
 
-    // three population buffers rotate (current row, row y+1, request for row y+2);
-    // the loop is unrolled by three so that no finished request is copied (a copy
-    // waits for every load in flight)
-    float fa[9], fb[9], fc[9];
+    // FP32 moments of a pulled row (zero at solid nodes): formed when the row
+    // arrives, they give the row's entry in Q (drho) and, a row later, the
+    // collision's input, so only the request buffers hold populations
+    auto moments_row = [&](const float (&f)[9], bool fluid, unsigned sm) {
+        return fluid ? moments_of(f, sm != 0u) : Mom<float>{0.f, 0.f, 0.f, 0.f, 0.f};
+    };
+    // Requests run one row ahead of the arithmetic; the two request buffers swap
+    // roles every row (the loop is unrolled by two), so a finished request is
+    // never copied (a copy waits for every load in flight).
+    float fa[9], fb[9];
     RowInfo ri = row_info(g, s.ya - 1);
     bool fl = !(L.t0 && ri.w0);
-    pull_lane(fs, L, ri, solid_bits(L, ri), fa);
-    Q[r3(-1)][k] = fl ? sum9(fa) : 0.f;
+    unsigned sm = solid_bits(L, ri);
+    pull_lane(fs, L, ri, sm, fa);
+    Q[r3(-1)][k] = moments_row(fa, fl, sm).drho;
     ri = row_info(g, s.ya);
     unsigned sm_cur = solid_bits(L, ri);
     bool fl_cur = !(L.t0 && ri.w0);
     pull_lane(fs, L, ri, sm_cur, fa);
-    Q[r3(0)][k] = fl_cur ? sum9(fa) : 0.f;
+    Mom<float> mom_cur = moments_row(fa, fl_cur, sm_cur);
+    Q[r3(0)][k] = mom_cur.drho;
     RowInfo ri_n = row_info(g, s.ya + 1);
     unsigned sm_n = solid_bits(L, ri_n);
     bool fl_n = !(L.t0 && ri_n.w0);
     pull_lane(fs, L, ri_n, sm_n, fb);
 
-    auto iter = [&](int y, const float (&f)[9], const float (&fn)[9], float (&fp)[9]) {
+    // one row y: fn holds the request for row y+1, fp receives the one for row y+2
+    auto iter = [&](int y, const float (&fn)[9], float (&fp)[9]) {
         // request for row y+2; in the last row of the chunk it repeats the previous
         // one (cache hits, unused): a load under a branch would make every later
         // wait a wait for all loads
@@ -519,7 +528,8 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
         pull_lane(fs, L, ri_p, sm_p, fp);
         // keep the uses of the previous requests below the new ones
         __builtin_amdgcn_sched_barrier(0);
-        Q[r3(1)][k] = fl_n ? sum9(fn) : 0.f;
+        const Mom<float> mom_n = moments_row(fn, fl_n, sm_n);
+        Q[r3(1)][k] = mom_n.drho;
         wave_sync();
         if (out_col && fl_cur) {
             float dxf, dyf, lapf;
@@ -536,10 +546,7 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
             stencil3(Q[r3(-1)], Q[r3(0)], Q[r3(1)], k, sm_cur, G2, dxf, dyf, lapf);
             const bool bnd = sm_cur != 0u;
             const CT F = (FORCE && !bnd) ? (CT)cd.Fx : CT(0);
-            CT fcur[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fcur[i] = (CT)f[i];
-            const Mom<CT> m = moments_of(fcur, bnd);
+            const Mom<CT> m{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
             const CT rho_ref = (CT)cd.rho_ref;
             const CT rho = rho_ref + m.drho;
             const CT inv_rho = recip(rho);
@@ -564,15 +571,14 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
         fl_cur = fl_n;
         sm_n = sm_p;
         fl_n = fl_p;
+        mom_cur = mom_n;
         p3 = p3 == 2 ? 0 : p3 + 1;
         wave_sync();
     };
-    for (int y = s.ya; y < s.yb; y += 3) {
-        iter(y, fa, fb, fc);
+    for (int y = s.ya; y < s.yb; y += 2) {
+        iter(y, fb, fa);
         if (y + 1 >= s.yb) break;
-        iter(y + 1, fb, fc, fa);
-        if (y + 2 >= s.yb) break;
-        iter(y + 2, fc, fa, fb);
+        iter(y + 1, fa, fb);
     }
 }
 

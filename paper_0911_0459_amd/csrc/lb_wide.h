@@ -300,28 +300,38 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
     const float G2 = 2.f * c.G;
     const int yo = 4;   // rows are addressed in the ring as y + 4 (y >= ya - 1 >= -1)
     auto s4 = [](int y) { return y & 3; };
-    auto q_store = [&](int sl, bool fluid, const float (&f)[9]) {
-        if (W.um) Q[sl][uj] = fluid ? sum9(f) : 0.f;
+    auto q_store = [&](int slot, float drho) {
+        if (W.um) Q[slot][uj] = drho;
     };
 
-    // three population buffers rotate (current row, row y+1, request for row y+2);
-    // the loop is unrolled by three so that no finished request is copied
-    float fa[9], fb[9], fc[9];
+    // FP32 moments of a pulled row (zero at solid nodes): formed when the row
+    // arrives, they give the row's entry in Q (drho) and, a row later, the
+    // collision's input, so only the request buffers hold populations
+    auto moments_row = [&](const float (&f)[9], bool fluid, unsigned sm) {
+        return fluid ? moments_of(f, sm != 0u) : Mom<float>{0.f, 0.f, 0.f, 0.f, 0.f};
+    };
+    // Requests run one row ahead of the arithmetic; the two request buffers swap
+    // roles every row (the loop is unrolled by two), so a finished request is
+    // never copied: a copy would wait for every load in flight.
+    float fa[9], fb[9];
     RowInfo ri = row_info(g, s.ya - 1);
     bool fl = !(L.t0 && ri.w0);
-    pull_lane(fs, L, ri, solid_bits(L, ri), fa);
-    q_store(s4(s.ya - 1 + yo), fl, fa);
+    unsigned sm = solid_bits(L, ri);
+    pull_lane(fs, L, ri, sm, fa);
+    q_store(s4(s.ya - 1 + yo), moments_row(fa, fl, sm).drho);
     ri = row_info(g, s.ya);
     unsigned sm_cur = solid_bits(L, ri);
     bool fl_cur = !(L.t0 && ri.w0);
     pull_lane(fs, L, ri, sm_cur, fa);
-    q_store(s4(s.ya + yo), fl_cur, fa);
+    Mom<float> mom_cur = moments_row(fa, fl_cur, sm_cur);
+    q_store(s4(s.ya + yo), mom_cur.drho);
     RowInfo ri_n = row_info(g, s.ya + 1);
     unsigned sm_n = solid_bits(L, ri_n);
     bool fl_n = !(L.t0 && ri_n.w0);
     pull_lane(fs, L, ri_n, sm_n, fb);
 
-    auto iter = [&](int y, const float (&f)[9], const float (&fn)[9], float (&fp)[9]) {
+    // one row y: fn holds the request for row y+1, fp receives the one for row y+2
+    auto iter = [&](int y, const float (&fn)[9], float (&fp)[9]) {
         const int yr = y + yo;
         // request for row y+2 (in the last row of the chunk a repeat of the
         // previous one: cache hits, unused)
@@ -330,7 +340,8 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
         const bool fl_p = !(L.t0 && ri_p.w0);
         pull_lane(fs, L, ri_p, sm_p, fp);
         __builtin_amdgcn_sched_barrier(0);
-        q_store(s4(yr + 1), fl_n, fn);
+        const Mom<float> mom_n = moments_row(fn, fl_n, sm_n);
+        q_store(s4(yr + 1), mom_n.drho);
         lds_barrier();
         if (out_col && fl_cur) {
             float dxf, dyf, lapf;
@@ -347,10 +358,7 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
             stencil3(Q[s4(yr - 1)], Q[s4(yr)], Q[s4(yr + 1)], uj, sm_cur, G2, dxf, dyf, lapf);
             const bool bnd = sm_cur != 0u;
             const CT F = (FORCE && !bnd) ? (CT)cd.Fx : CT(0);
-            CT fcur[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) fcur[i] = (CT)f[i];
-            const Mom<CT> m = moments_of(fcur, bnd);
+            const Mom<CT> m{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
             const CT rho_ref = (CT)cd.rho_ref;
             const CT rho = rho_ref + m.drho;
             const CT inv_rho = recip(rho);
@@ -371,17 +379,16 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
         }
+        mom_cur = mom_n;
         sm_cur = sm_n;
         fl_cur = fl_n;
         sm_n = sm_p;
         fl_n = fl_p;
     };
-    for (int y = s.ya; y < s.yb; y += 3) {
-        iter(y, fa, fb, fc);
+    for (int y = s.ya; y < s.yb; y += 2) {
+        iter(y, fb, fa);
         if (y + 1 >= s.yb) break;
-        iter(y + 1, fb, fc, fa);
-        if (y + 2 >= s.yb) break;
-        iter(y + 2, fc, fa, fb);
+        iter(y + 1, fa, fb);
     }
 }
 
