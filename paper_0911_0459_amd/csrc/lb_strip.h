@@ -12,13 +12,14 @@
 // pipelining), which keeps enough loads in flight per wave to cover HBM
 // latency without a large occupancy.
 //
-// The collision (moments, velocity, relaxation, reconstruction) is evaluated in
-// the arithmetic type CT (double by default): the shifted FP32 populations are
-// stored as before, but in FP32 arithmetic the rounding of the reconstructed
-// populations of a steady flow repeats every step at every node and acts like
-// a small spurious body force, which shifts a moving meniscus by ~1e-4 lattice
-// units per 1e4 steps.  The order-parameter path (mu, g^eq, phi update) is
-// FP32: its rounding does not accumulate that way.
+// The collision (velocity, equilibrium, relaxation, reconstruction) is
+// evaluated in the arithmetic type CT (double by default) from the FP32 moments
+// of the pulled populations: the shifted FP32 populations are stored as
+// before, but in FP32 arithmetic the rounding of the reconstructed populations
+// of a steady flow repeats every step at every node and acts like a small
+// spurious body force, which shifts a moving meniscus by ~1e-4 lattice units
+// per 1e4 steps.  The order-parameter path (mu, g^eq, phi update) is FP32: its
+// rounding does not accumulate that way.
 #pragma once
 #include "lb_kernels.h"
 
