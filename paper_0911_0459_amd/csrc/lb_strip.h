@@ -289,7 +289,9 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
     __shared__ float UX[3][SW], UY[3][SW], AM[3][SW];
 
     const int k = threadIdx.x;
-    const int xl = s.xs + k - 1;
+    // lanes past column nx+1 (the last one that an output column reads) of the
+    // row's last strip repeat that column: their loads share its addresses
+    const int xl = min(s.xs + k - 1, g.nx + 1);
     const LaneCols L = lane_cols(g, xl);
     const bool out_col = k >= 1 && k <= STRIP_OUT && xl < g.nx;
     // the two extra phi columns, xs-2 (lane 0) and xs+63 (lane 1)
@@ -485,7 +487,9 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
 
     __shared__ float Q[3][SW];         // drho rows, column xs-1+k at lane k
     const int k = threadIdx.x;
-    const int xl = s.xs + k - 1;
+    // lanes past column nx+1 (the last one that an output column reads) of the
+    // row's last strip repeat that column: their loads share its addresses
+    const int xl = min(s.xs + k - 1, g.nx + 1);
     const LaneCols L = lane_cols(g, xl);
     const bool out_col = k >= 1 && k <= STRIP_OUT && xl < g.nx;
     const float G2 = 2.f * c.G;

@@ -100,7 +100,9 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     __shared__ float RG[RING][4][WP];
 
     const WideLane W = wide_lane();
-    const int xl = s.xs + W.dx;
+    // lanes past column nx+1 (the last one that an output column reads) of the
+    // row's last strip repeat that column: their loads share its addresses
+    const int xl = min(s.xs + W.dx, g.nx + 1);
     const LaneCols L = lane_cols(g, xl);
     const bool out_col = W.main && xl < g.nx;
     const int pj = W.pj, qj = W.qj;
@@ -293,7 +295,9 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
     // y-1..y+1, then waits at row y+1's barrier
     __shared__ float Q[4][WU];
     const WideLane W = wide_lane();
-    const int xl = s.xs + W.dx;
+    // lanes past column nx+1 (the last one that an output column reads) of the
+    // row's last strip repeat that column: their loads share its addresses
+    const int xl = min(s.xs + W.dx, g.nx + 1);
     const LaneCols L = lane_cols(g, xl);
     const bool out_col = W.main && xl < g.nx;
     const int uj = W.uj;
