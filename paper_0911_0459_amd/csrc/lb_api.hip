@@ -157,7 +157,9 @@ int count_tiles(const lb_geometry& g, int rows) {
 }
 
 // Strips of STRIP_OUT output columns; a strip lying entirely in the tube
-// section only covers the channel rows.  chunk = 0 keeps whole strips.
+// section only covers the channel rows, and one that the tube enters or leaves
+// covers the channel rows, with its wall rows in strips of their own over the
+// reservoir columns.  chunk = 0 keeps whole strips.
 constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
 constexpr size_t LB_STRIP_GROUP = 16;  // neighbouring strip columns listed chunk by chunk
 constexpr size_t LB_TAIL_COLS = 32;    // columns per XCD run whose last rows go to short chunks
@@ -182,19 +184,40 @@ constexpr size_t LB_TAIL_COLS = 32;    // columns per XCD run whose last rows go
 // xcd_start[x] .. xcd_start[x + 1] is XCD x's run.
 void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk, int width,
                   int align, std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
-    struct Col { int cap, xs, ya, yb; };
+    struct Col { int cap, xs, xe, ya, yb; };
     std::vector<Col> cols;
     long long rows = 0;
+    auto add = [&](int k, int xs, int xe, int ya, int yb) {
+        cols.push_back(Col{k, xs, xe, ya, yb});
+        rows += yb - ya;
+    };
     for (size_t k = 0; k < G.size(); ++k) {
         if (!active[k]) continue;
         const lb_geometry& g = G[k];
+        const bool tube = g.tube_len > 0;
+        const int te = g.x_in + g.tube_len;
         for (int xs = 0; xs < g.nx; xs += width) {
             const int xe = std::min(xs + width, g.nx);
-            const bool in_tube = g.tube_len > 0 && xs >= g.x_in && xe <= g.x_in + g.tube_len;
-            const int ya = in_tube ? g.y0 : 0;
-            const int yb = in_tube ? g.y0 + g.tube_h : g.ny;
-            cols.push_back(Col{(int)k, xs, ya, yb});
-            rows += yb - ya;
+            if (tube && xs >= g.x_in && xe <= te) {
+                add((int)k, xs, xe, g.y0, g.y0 + g.tube_h);
+                continue;
+            }
+            // The tube enters (or leaves) the column: its wall rows hold fluid only in
+            // the reservoir columns [rs, re), cut at a multiple of 32 columns so that
+            // every strip's stores still cover whole 128-byte lines.
+            int rs = xs, re = xs;
+            if (tube && xs < g.x_in && g.x_in < xe && xe <= te) re = std::min(xe, (g.x_in + 31) / 32 * 32);
+            if (tube && g.x_in <= xs && xs < te && te < xe) rs = std::max(xs, te / 32 * 32), re = xe;
+            if (re - rs <= 0 || re - rs >= xe - xs) {
+                add((int)k, xs, xe, 0, g.ny);
+                continue;
+            }
+            // channel rows over the whole width; with an odd tube height one wall row
+            // more, so that the wall strip above starts on the channel's row parity
+            const int yc = std::min(g.ny, g.y0 + g.tube_h + (g.tube_h & 1));
+            add((int)k, xs, xe, g.y0, yc);
+            if (g.y0 > 0) add((int)k, rs, re, 0, g.y0);
+            if (yc < g.ny) add((int)k, rs, re, yc, g.ny);
         }
     }
     auto down = [&](int v) { return v - v % align; };
@@ -227,7 +250,7 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
             const size_t g1 = std::min(ci, g0 + LB_STRIP_GROUP);
             if (chunk <= 0) {
                 for (size_t j = g0; j < g1; ++j) {
-                    if (out) out->push_back(StripDev{cols[j].cap, cols[j].xs, cols[j].ya, cols[j].yb});
+                    if (out) out->push_back(StripDev{cols[j].cap, cols[j].xs, cols[j].xe, cols[j].ya, cols[j].yb});
                     ++n;
                 }
                 continue;
@@ -239,7 +262,7 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
                     any = true;
                     const int y0 = cols[j].ya + start_of(j, k), y1 = cols[j].ya + start_of(j, k + 1);
                     if (y0 == y1) continue;   // (rounding to align emptied it)
-                    if (out) out->push_back(StripDev{cols[j].cap, cols[j].xs, y0, y1});
+                    if (out) out->push_back(StripDev{cols[j].cap, cols[j].xs, cols[j].xe, y0, y1});
                     ++n;
                 }
                 if (!any) break;
@@ -248,7 +271,7 @@ void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& act
         for (size_t j = tail_from; j < ci; ++j) {
             const Col& c = cols[j];
             for (int y = c.ya + body_of(j); y < c.yb; y += small) {
-                tails.push_back(StripDev{c.cap, c.xs, y, std::min(y + small, c.yb)});
+                tails.push_back(StripDev{c.cap, c.xs, c.xe, y, std::min(y + small, c.yb)});
                 ++n;
             }
         }

@@ -30,7 +30,9 @@ constexpr int SW = 64;            // lanes per strip = one wavefront
 constexpr int PHW = SW + 2;       // phi row in LDS: columns xs-2 .. xs+63
 
 struct StripDev {
-    int cap, xs, ya, yb;          // output columns [xs, xs+62), output rows [ya, yb)
+    int cap;
+    int xs, xe;                   // output columns [xs, xe): at most 62, or 192 in a wide strip
+    int ya, yb;                   // output rows [ya, yb), ya >= 0, yb <= ny
 };
 
 struct StripArgs {
@@ -289,11 +291,11 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
     __shared__ float UX[3][SW], UY[3][SW], AM[3][SW];
 
     const int k = threadIdx.x;
-    // lanes past column nx+1 (the last one that an output column reads) of the
-    // row's last strip repeat that column: their loads share its addresses
-    const int xl = min(s.xs + k - 1, g.nx + 1);
+    // lanes past column xe+1 (the last one that an output column reads) repeat
+    // that column: their loads share its addresses
+    const int xl = min(s.xs + k - 1, s.xe + 1);
     const LaneCols L = lane_cols(g, xl);
-    const bool out_col = k >= 1 && k <= STRIP_OUT && xl < g.nx;
+    const bool out_col = k >= 1 && k <= STRIP_OUT && xl < s.xe;
     // the two extra phi columns, xs-2 (lane 0) and xs+63 (lane 1)
     const int ce = wrap_mod(k == 0 ? s.xs - 2 : s.xs + SW - 1, g.nx);
     const bool te = g.tube_col(ce);
@@ -487,11 +489,11 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
 
     __shared__ float Q[3][SW];         // drho rows, column xs-1+k at lane k
     const int k = threadIdx.x;
-    // lanes past column nx+1 (the last one that an output column reads) of the
-    // row's last strip repeat that column: their loads share its addresses
-    const int xl = min(s.xs + k - 1, g.nx + 1);
+    // lanes past column xe+1 (the last one that an output column reads) repeat
+    // that column: their loads share its addresses
+    const int xl = min(s.xs + k - 1, s.xe + 1);
     const LaneCols L = lane_cols(g, xl);
-    const bool out_col = k >= 1 && k <= STRIP_OUT && xl < g.nx;
+    const bool out_col = k >= 1 && k <= STRIP_OUT && xl < s.xe;
     const float G2 = 2.f * c.G;
     int p3 = 0;   // slot of row ya-1
     auto r3 = [&](int d) { int v = p3 + 1 + d; v -= v >= 3 ? 3 : 0; v -= v >= 3 ? 3 : 0; return v; };

@@ -100,11 +100,11 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     __shared__ float RG[RING][4][WP];
 
     const WideLane W = wide_lane();
-    // lanes past column nx+1 (the last one that an output column reads) of the
-    // row's last strip repeat that column: their loads share its addresses
-    const int xl = min(s.xs + W.dx, g.nx + 1);
+    // lanes past column xe+1 (the last one that an output column reads) repeat
+    // that column: their loads share its addresses
+    const int xl = min(s.xs + W.dx, s.xe + 1);
     const LaneCols L = lane_cols(g, xl);
-    const bool out_col = W.main && xl < g.nx;
+    const bool out_col = W.main && xl < s.xe;
     const int pj = W.pj, qj = W.qj;
     const float G2 = 2.f * c.G;
     const float kap = c.kappa, Gam = c.Gamma;
@@ -295,11 +295,11 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
     // y-1..y+1, then waits at row y+1's barrier
     __shared__ float Q[4][WU];
     const WideLane W = wide_lane();
-    // lanes past column nx+1 (the last one that an output column reads) of the
-    // row's last strip repeat that column: their loads share its addresses
-    const int xl = min(s.xs + W.dx, g.nx + 1);
+    // lanes past column xe+1 (the last one that an output column reads) repeat
+    // that column: their loads share its addresses
+    const int xl = min(s.xs + W.dx, s.xe + 1);
     const LaneCols L = lane_cols(g, xl);
-    const bool out_col = W.main && xl < g.nx;
+    const bool out_col = W.main && xl < s.xe;
     const int uj = W.uj;
     const float G2 = 2.f * c.G;
     const int yo = 4;   // rows are addressed in the ring as y + 4 (y >= ya - 1 >= -1)

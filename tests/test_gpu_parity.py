@@ -133,6 +133,39 @@ def test_wide_strips_across_strip_boundaries(L, model):
     assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (drho, dphi, du)
 
 
+@pytest.mark.parametrize("model", ["vdw", "binary"])
+def test_strips_that_the_tube_enters_or_leaves(L, model):
+    """520x41 lattice, reservoirs on both sides of the tube (inlet at 150,
+    outlet at 430, neither on a 32-column boundary), odd tube height and wall
+    thickness. The strips that the tube enters or leaves sweep their channel
+    rows, and their wall rows in strips of their own over the reservoir
+    columns. Against the oracle (as are the tiles), the one-wavefront strips
+    (to rounding), and across chunkings (bitwise)."""
+    g = I.Geometry(nx=520, ny=41, x_in=150, tube_len=280, tube_h=15, y0=13)
+    if model == "vdw":
+        w = I.Workload("vdw_ends", "vdw", g, 0, 0, seed=33, nu_l=0.13, nu_g=0.13, wall_grad=-0.1,
+                       liquid=4.5, gas=2.6, **I.VDW_CONSTS)
+    else:
+        nl, ng = I.viscosity_pair(20.0)
+        w = I.Workload("bin_ends", "binary", g, 0, 0, seed=34, nu_l=nl, nu_g=ng, theta_deg=50.0,
+                       liquid=1.0, gas=-1.0, **I.BIN_CONSTS)
+    wide, _ = gpu_run(L, w, 200, cfg=dict(schedule=4, chunk_rows=0, fp64_arith=1))
+    orc, _ = run_oracle(w, 200)
+    drho, dphi, du = field_errors(w, wide, orc)
+    assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (drho, dphi, du)
+    for cfg in (dict(schedule=4, chunk_rows=5), dict(schedule=4, chunk_rows=12)):
+        got, _ = gpu_run(L, w, 200, cfg=dict(cfg, fp64_arith=1))
+        for x, y in zip(wide, got):
+            assert np.array_equal(x, y), cfg
+    narrow, _ = gpu_run(L, w, 200, cfg=dict(schedule=3, chunk_rows=6, fp64_arith=1))
+    gap = max(float(np.abs(x - y).max()) for x, y in zip(wide, narrow))
+    print(f"{model}: wide vs one-wavefront strips, max |difference| {gap:.3e}")
+    assert gap <= 1e-6
+    tile, _ = gpu_run(L, w, 200, cfg=dict(tile_rows=4, schedule=1, fp64_arith=1))
+    drho, dphi, du = field_errors(w, tile, orc)
+    assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, ("tiles", drho, dphi, du)
+
+
 @pytest.mark.parametrize("cfg", [dict(schedule=4, chunk_rows=0), dict(schedule=4, chunk_rows=4),
                                  dict(schedule=3, chunk_rows=0), dict(tile_rows=2, schedule=1)],
                          ids=["wide", "wide-ch4", "strip", "tile"])
