@@ -33,11 +33,15 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"vdw": 72, "binary": 80}   # read + write of every stored FP32 value (9 f; binary + phi)
 
 
+# the step kernels and the strip table that shapes their traffic
+KERNEL_SOURCES = ("lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_strip_table.h", "lb_wide.h")
+
+
 def kernel_source_hash() -> str:
     """Hash of the sources of the step kernels (the counter summary in
     profiles/ is only used while it matches)."""
     h = hashlib.sha256()
-    for name in ("lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_wide.h"):
+    for name in KERNEL_SOURCES:
         h.update(open(os.path.join(ROOT, "paper_0911_0459_amd", "csrc", name), "rb").read())
     return h.hexdigest()[:16]
 

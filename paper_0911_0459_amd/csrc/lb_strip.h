@@ -22,18 +22,13 @@
 // rounding does not accumulate that way.
 #pragma once
 #include "lb_kernels.h"
+#include "lb_strip_table.h"
 
 namespace lbk {
 
 constexpr int STRIP_OUT = 62;     // output columns per strip
 constexpr int SW = 64;            // lanes per strip = one wavefront
 constexpr int PHW = SW + 2;       // phi row in LDS: columns xs-2 .. xs+63
-
-struct StripDev {
-    int cap;
-    int xs, xe;                   // output columns [xs, xe): at most 62, or 192 in a wide strip
-    int ya, yb;                   // output rows [ya, yb), ya >= 0, yb <= ny
-};
 
 struct StripArgs {
     const CapDev* caps;
