@@ -253,13 +253,9 @@ lb_status make_layout(int n, const lb_params* P, const lb_geometry* G, Layout& L
     }
     L.arena_floats = off;
     {
-        std::vector<lb_geometry> gv(G, G + n);
-        std::vector<int> all(n, 1);
-        // the finest chunking allowed, for either strip width
-        int narrow = 0, wide = 0;
-        build_strips(gv, all, LB_MIN_CHUNK, STRIP_OUT, 1, nullptr, &narrow);
-        build_strips(gv, all, LB_MIN_CHUNK, WIDE_OUT, 1, nullptr, &wide);
-        L.max_strips = std::max(narrow, wide);
+        // room for the strip table of either width at any chunking
+        const std::vector<lb_geometry> gv(G, G + n);
+        L.max_strips = std::max(strip_capacity(gv, STRIP_OUT), strip_capacity(gv, WIDE_OUT));
     }
     size_t o = 0;
     L.off_caps = o;

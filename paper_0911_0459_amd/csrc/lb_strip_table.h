@@ -22,17 +22,19 @@ struct StripDev {
 // keeps whole strips.
 constexpr int LB_MIN_CHUNK = 4;   // smallest rows per strip chunk
 constexpr size_t LB_STRIP_GROUP = 16;  // neighbouring strip columns listed chunk by chunk
-constexpr size_t LB_TAIL_COLS = 32;    // columns per XCD run whose last rows go to short chunks
+constexpr int LB_TAIL_MIN_CHUNK = 12;  // chunks from this height on end each XCD run with short chunks
+constexpr size_t LB_TAIL_COLS = 64;    // columns per XCD run whose last rows go to short chunks
 
 // Strip table of the row-sweep kernels.  Every strip column (width output
 // columns of one capillary, over the rows that hold fluid) is cut into
 // ceil(rows / chunk) chunks of balanced height (no short remainder chunk, whose
 // prologue would cost as much as a full chunk's).  The columns are dealt to the
-// 8 XCDs in contiguous runs of about equal row count.  For chunks of 16 rows or
-// more, the last 2 * small rows of the last LB_TAIL_COLS columns of each run
-// are cut into chunks of small = max(4, chunk / 4) rows and listed at the end
-// of the run, so that a step ends on short strips (a small tail) while most
-// rows go through long strips (few prologues, little re-read at chunk edges).
+// 8 XCDs in contiguous runs of about equal row count.  For chunks of
+// LB_TAIL_MIN_CHUNK rows or more, the last 2 * small rows of the last
+// LB_TAIL_COLS columns of each run are cut into chunks of small =
+// max(4, chunk / 4) rows and listed at the end of the run, so that a step ends
+// on short strips (a small tail) while most rows go through long strips (few
+// prologues, little re-read at chunk edges).
 // Within a run, groups of LB_STRIP_GROUP neighbouring columns are listed chunk
 // by chunk across the group, so that strips sharing halo columns run at the
 // same time, and the chunks of one column share an L2.
@@ -93,8 +95,9 @@ inline void build_strips(const std::vector<lb_geometry>& G, const std::vector<in
         tails.clear();
         const size_t c0 = ci;
         for (; ci < cols.size() && (done < goal || x == 7); ++ci) done += cols[ci].yb - cols[ci].ya;
-        // (chunks below 16 rows are short enough to end a step without a tail)
-        const size_t tail_from = chunk < 16 ? ci : (ci - c0 > LB_TAIL_COLS ? ci - LB_TAIL_COLS : c0);
+        // (shorter chunks end a step without a tail: at 8 rows, tails measured slower)
+        const size_t tail_from =
+            chunk < LB_TAIL_MIN_CHUNK ? ci : (ci - c0 > LB_TAIL_COLS ? ci - LB_TAIL_COLS : c0);
         // rows of column j before its tail (a multiple of align when a tail follows)
         auto body_of = [&](size_t j) {
             const int r = cols[j].yb - cols[j].ya;
@@ -139,6 +142,19 @@ inline void build_strips(const std::vector<lb_geometry>& G, const std::vector<in
     }
     if (xcd_start) xcd_start[8] = n;
     if (count) *count = n;
+}
+
+// Strips that a table of this width may need, at any chunking the library
+// accepts (0, or 4 rows and more) and for any set of active capillaries: a
+// column of r rows has at most ceil(r / 4) chunks, and one more where a tail
+// cuts its last rows into chunks of their own (the body and the tail each
+// rounded up: ceil(a / 4) + ceil(b / 4) <= ceil((a + b) / 4) + 1).
+inline int strip_capacity(const std::vector<lb_geometry>& G, int width) {
+    const std::vector<int> all(G.size(), 1);
+    int fine = 0, columns = 0;
+    build_strips(G, all, LB_MIN_CHUNK, width, 1, nullptr, &fine);
+    build_strips(G, all, 0, width, 1, nullptr, &columns);
+    return fine + columns;
 }
 
 }  // namespace lbk

@@ -1,6 +1,7 @@
 // CPU check of the row-sweep strip table (lb_strip_table.h), built with g++.
-// Reads geometries from stdin (a count, then "nx ny x_in tube_len tube_h y0
-// active" per line) and prints one line per property checked, "name value".
+// Reads geometries from stdin ("count mode", then "nx ny x_in tube_len tube_h
+// y0 active" per line; mode 0 checks one table of all of them, mode 1 a table
+// of each one alone) and prints one line per property checked, "name value".
 #include <algorithm>
 #include <cstdio>
 #include <map>
@@ -15,23 +16,20 @@ static bool solid(const lb_geometry& g, int x, int y) {
     return g.tube_len > 0 && x >= g.x_in && x < g.x_in + g.tube_len && (y < g.y0 || y >= g.y0 + g.tube_h);
 }
 
-int main() {
-    int n = 0;
-    if (std::scanf("%d", &n) != 1 || n <= 0) return 2;
-    std::vector<lb_geometry> G(n);
-    std::vector<int> active(n);
-    for (int k = 0; k < n; ++k) {
-        lb_geometry g{};
-        if (std::scanf("%d %d %d %d %d %d %d", &g.nx, &g.ny, &g.x_in, &g.tube_len, &g.tube_h, &g.y0, &active[k]) != 7)
-            return 2;
-        G[k] = g;
-    }
+struct Counts {
     long long bad_bounds = 0, bad_align32 = 0, twice = 0, missed = 0, inactive = 0, bad_parity = 0, bad_xcd = 0;
     long long over_capacity = 0, max_extra = 0;
+};
+
+static void check(const std::vector<lb_geometry>& G, const std::vector<int>& active, Counts& r) {
+    const int n = (int)G.size();
+    long long &bad_bounds = r.bad_bounds, &bad_align32 = r.bad_align32, &twice = r.twice, &missed = r.missed;
+    long long &inactive = r.inactive, &bad_parity = r.bad_parity, &bad_xcd = r.bad_xcd;
+    long long &over_capacity = r.over_capacity, &max_extra = r.max_extra;
     for (int width : {62, 192}) {
-        int cap_count = 0;
-        lbk::build_strips(G, active, lbk::LB_MIN_CHUNK, width, 1, nullptr, &cap_count);
-        for (int chunk : {0, 4, 5, 12, 16, 32}) {
+        // the capacity the library allocates (every capillary active)
+        const int cap_count = lbk::strip_capacity(G, width);
+        for (int chunk : {0, 4, 5, 6, 8, 11, 12, 16, 24, 32, 4096}) {
             std::vector<StripDev> S;
             int count = -1, xcd[9];
             lbk::build_strips(G, active, chunk, width, 2, &S, &count, xcd);
@@ -86,9 +84,28 @@ int main() {
             }
         }
     }
-    std::printf("bad_bounds %lld\nbad_align32 %lld\ntwice %lld\nmissed %lld\ninactive %lld\n", bad_bounds,
-                bad_align32, twice, missed, inactive);
-    std::printf("bad_parity %lld\nbad_xcd %lld\nover_capacity %lld\nmax_extra_solid %lld\n", bad_parity, bad_xcd,
-                over_capacity, max_extra);
+}
+
+int main() {
+    int n = 0, mode = 0;
+    if (std::scanf("%d %d", &n, &mode) != 2 || n <= 0) return 2;
+    std::vector<lb_geometry> G(n);
+    std::vector<int> active(n);
+    for (int k = 0; k < n; ++k) {
+        lb_geometry g{};
+        if (std::scanf("%d %d %d %d %d %d %d", &g.nx, &g.ny, &g.x_in, &g.tube_len, &g.tube_h, &g.y0, &active[k]) != 7)
+            return 2;
+        G[k] = g;
+    }
+    Counts r;
+    if (mode == 0) {
+        check(G, active, r);
+    } else {
+        for (int k = 0; k < n; ++k) check({G[k]}, {active[k]}, r);
+    }
+    std::printf("bad_bounds %lld\nbad_align32 %lld\ntwice %lld\nmissed %lld\ninactive %lld\n", r.bad_bounds,
+                r.bad_align32, r.twice, r.missed, r.inactive);
+    std::printf("bad_parity %lld\nbad_xcd %lld\nover_capacity %lld\nmax_extra_solid %lld\n", r.bad_parity,
+                r.bad_xcd, r.over_capacity, r.max_extra);
     return 0;
 }

@@ -3,7 +3,7 @@ every fluid node of every active capillary is swept exactly once, strips stay
 inside their lattice, wide strips start on 32-column boundaries (whole
 128-byte lines), chunks start an even number of rows into their column (the
 kernels' row loops are unrolled by two), the table never outgrows the capacity
-the library allocates, and the solid walls of the tube are not swept (beyond
+the library allocates (at any chunking, for one capillary or a batch), and the solid walls of the tube are not swept (beyond
 one wall row and the rounding of the cut to 32 columns where the tube enters or
 leaves a strip)."""
 import os
@@ -41,8 +41,9 @@ def checker(tmp_path_factory):
     return exe
 
 
-def run(exe, geoms):
-    text = f"{len(geoms)}\n" + "".join(" ".join(str(v) for v in g) + "\n" for g in geoms)
+def run(exe, geoms, alone=False):
+    """Check one strip table of all `geoms` (or, with alone, one table per geometry)."""
+    text = f"{len(geoms)} {int(alone)}\n" + "".join(" ".join(str(v) for v in g) + "\n" for g in geoms)
     r = subprocess.run([exe], input=text, capture_output=True, text=True, timeout=600, check=True)
     return {k: int(v) for k, v in (line.split() for line in r.stdout.splitlines())}
 
@@ -55,6 +56,14 @@ def expect_clean(res):
 
 def test_edge_geometries(checker):
     expect_clean(run(checker, [(*g, 1) for g in EDGE_CASES]))
+
+
+def test_each_geometry_alone(checker):
+    """One capillary per table (as the sequential runs and the autotuner of a
+    single lattice build it): every column of an XCD run may end in a tail."""
+    sweep = [(w.geom.nx, w.geom.ny, w.geom.x_in, w.geom.tube_len, w.geom.tube_h, w.geom.y0)
+             for w in I.sweep_batch()]
+    expect_clean(run(checker, [(*g, 1) for g in EDGE_CASES + sweep], alone=True))
 
 
 def test_sweep_batch_with_retired_capillaries(checker):
