@@ -238,6 +238,8 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *  chunk_rows: target rows per strip chunk for schedules 3 and 4 (0, or 4..4096;
  *    default 8): each strip column is cut into chunks of about that height that
  *    start an even number of rows apart, so that the results do not depend on it.
+ *    From 12 rows on, the last rows of the last columns of each XCD's run go to
+ *    short chunks (a quarter of the height, at least 4 rows) that end the step.
  *  graph_steps: steps captured per HIP graph (even, >= 2; 0 = no graphs).
  *  fp64_arith: 1 evaluates the collision in FP64 (schedules 3, 4; schedules 0..2
  *    then compute the whole step in FP64), 0 in FP32.  The stored state is FP32
