@@ -406,6 +406,30 @@ def test_autotune_keeps_state(L):
         assert np.array_equal(x, y)
 
 
+def test_every_strip_chunking_fits_one_capillary(L):
+    """Sweep capillary 144 alone (an 11-row tube): with tail chunks a column
+    can need one strip more than at the finest chunking. Every row-sweep
+    chunking is accepted, and all give bitwise the same fields."""
+    w = I.sweep_capillary(4, 144)
+    assert w.geom.tube_h == 11
+    lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), w.initial_field())
+    for schedule in (3, 4):
+        for ch in (0, 4, 6, 8, 12, 16, 32):
+            lat.set_launch_config(schedule=schedule, chunk_rows=ch, fp64_arith=1)
+        lat.set_launch_config(schedule=4, chunk_rows=12, fp64_arith=1)
+    lat.step(20)
+    ref = lat.moments()
+    lat.close()
+    for ch in (16, 32):
+        got, _ = gpu_run(L, w, 20, cfg=dict(schedule=4, chunk_rows=ch, fp64_arith=1))
+        for x, y in zip(ref, got):
+            assert np.array_equal(x, y), ch
+    tuned = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), w.initial_field())
+    cfg, us = tuned.autotune(trial_steps=4)
+    assert us > 0
+    tuned.close()
+
+
 def test_moments_device_matches_host(L):
     import torch
     w = small_binary(nx=130, ny=40, H=12)
