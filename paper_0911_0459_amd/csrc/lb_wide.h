@@ -1,18 +1,20 @@
 // Cooperative row-sweep ("wide strip") kernels of lbcap: the time step of
 // lb_strip_bin / lb_strip_vdw with every wavefront's output columns aligned to
-// whole 256-byte row segments.
+// whole 128-byte lines.
 //
-// A workgroup owns the WIDE_OUT = 192 output columns xs .. xs+191 of a chunk of
-// rows (xs a multiple of 192; rows are pitched to 64 floats, so each wavefront
-// stores whole cache lines and no line is shared with another workgroup) and
-// marches along y as the single-wave strips do.  Its NWM = 3 main wavefronts
-// produce the outputs, one column per lane.  The step at a column needs the
-// velocity and the chemical potential one column to either side and the order
-// field two columns to either side: a fourth (halo) wavefront computes the
-// velocity and the chemical potential of the columns xs-1 and xs+192 (lanes 0
-// and 1) and loads the order field of xs-2 and xs+193 (lanes 2 and 3); its
-// other lanes repeat lane 0's loads and store nothing.  Four wavefronts per
-// workgroup spread evenly over the four SIMDs of a CU.
+// A workgroup owns the output columns xs .. xe-1 (at most WIDE_OUT = 192) of a
+// chunk of rows (xs a multiple of 32; rows are pitched to 64 floats, so each
+// wavefront stores whole cache lines and no line is shared with another
+// workgroup) and marches along y as the single-wave strips do.  Its NWM = 3
+// main wavefronts produce the outputs, one column per lane.  The step at a
+// column needs the velocity and the chemical potential one column to either
+// side and the order field two columns to either side: a fourth (halo)
+// wavefront computes the velocity and the chemical potential of the columns
+// xs-1 and xs+192 (lanes 0 and 1) and loads the order field of xs-2 and xs+193
+// (lanes 2 and 3); its other lanes repeat lane 0's loads and store nothing.  In
+// a strip narrower than 192 columns, the main lanes at xe and xe+1 supply those
+// neighbours.  Four wavefronts per workgroup spread evenly over the four SIMDs
+// of a CU.
 //
 // Rows of phi, u and mu live in LDS rings shared by the four wavefronts.  The
 // wavefronts meet at LDS-only barriers (two per row for the binary model, one
