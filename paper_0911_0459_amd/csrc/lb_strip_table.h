@@ -45,7 +45,7 @@ constexpr size_t LB_TAIL_COLS = 64;    // columns per XCD run whose last rows go
 // chunking, and the results do not depend on it.
 // xcd_start[x] .. xcd_start[x + 1] is XCD x's run.
 inline void build_strips(const std::vector<lb_geometry>& G, const std::vector<int>& active, int chunk, int width,
-                  int align, std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
+                         int align, std::vector<StripDev>* out, int* count, int* xcd_start = nullptr) {
     struct Col { int cap, xs, xe, ya, yb; };
     std::vector<Col> cols;
     long long rows = 0;
