@@ -15,10 +15,13 @@
  *  - lattice units dx = dt = c = 1;
  *  - e5 = (1,1), e6 = (-1,-1), e7 = (-1,1), e8 = (1,-1), which makes the jx and jy
  *    rows of the Appendix A matrix the momentum components;
- *  - lambda (Eq. equilibrium, value not given): vdW (1/omega - 1/2)(1/3 - dp0/drho),
- *    binary 0; lambda_mode = 1 switches it off.  Parity unpinned: the paper
- *    gives no value to check it against (it vanishes at equilibrium, so the
- *    coexistence, Laplace and Young pins do not see it);
+ *  - lambda (Eq. equilibrium, value not given): for vdW the Chapman-Enskog
+ *    values that restore Galilean invariance under the Appendix A rates, one
+ *    for the traceless part of the bracket, (1/omega - 1/2)(1/3 - dp0/drho),
+ *    and one for its isotropic part, (1/2)(1/3 - dp0/drho) (equal to each other
+ *    at omega = 1, the printed single-lambda form); binary 0.  lambda_mode = 1
+ *    switches it off.  Pinned by the Galilean invariance of a translating
+ *    interface (see orc_feq), which only a moving state tests;
  *  - binary f^eq: the Eq. (equilibrium) form with X = p0 - kappa phi lap(phi) and the
  *    kappa terms in the gradients of phi, so that its second moment is the binary
  *    pressure tensor of Sec. 3.1 plus rho u u;
@@ -262,15 +265,20 @@ int orc_gradients(const orc_geom* g, double wall_grad, const double* q, double* 
 
 /* ---- equilibria, Appendix A ------------------------------------------------- */
 /* f^eq of Eq. (equilibrium) for i = 1..8 and Eq. (feq0) for i = 0.  X is the
- * isotropic part p0 - kappa q lap q; lambda multiplies the Galilean correction. */
-static void feq_general(double rho, double ux, double uy, double X, double lambda, double kappa,
-                        double dxq, double dyq, double* feq) {
+ * isotropic part p0 - kappa q lap q.  The Galilean correction
+ * lambda [u_a d_b q + u_b d_a q + delta_ab u.grad q] of Q is split into its
+ * traceless part [u_a d_b q + u_b d_a q - delta_ab u.grad q] and its isotropic
+ * part 2 delta_ab u.grad q, with coefficients lam_s and lam_b; the paper's form
+ * is lam_s = lam_b = lambda. */
+static void feq_general(double rho, double ux, double uy, double X, double lam_s, double lam_b,
+                        double kappa, double dxq, double dyq, double* feq) {
     double Q[2][2];
     double udq = ux * dxq + uy * dyq;
     double u[2] = {ux, uy}, dq[2] = {dxq, dyq};
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
-            Q[a][b] = rho * u[a] * u[b] + lambda * (u[a] * dq[b] + u[b] * dq[a] + (a == b ? udq : 0.0));
+            Q[a][b] = rho * u[a] * u[b] + lam_s * (u[a] * dq[b] + u[b] * dq[a] - (a == b ? udq : 0.0)) +
+                      lam_b * (a == b ? 2.0 * udq : 0.0);
     double sum = 0.0;
     for (int i = 1; i < 9; ++i) {
         double e[2] = {(double)EX[i], (double)EY[i]};
@@ -285,14 +293,36 @@ static void feq_general(double rho, double ux, double uy, double X, double lambd
     feq[0] = rho - sum;
 }
 
+/* lambda of the Galilean term (van der Waals model).  Chapman-Enskog: with a
+ * non-ideal p0 the first-order momentum flux keeps the term
+ *   -(tau - 1/2)(1/3 - dp0/drho)[u_a d_b rho + u_b d_a rho + delta_ab u.grad rho],
+ * tau being the relaxation time of the moments that carry it.  With the rates
+ * of Appendix A, S = diag(0,1,1,0,1,0,1,omega,omega), the traceless part of the
+ * second moment relaxes at omega (tau = 1/omega) and its trace, the energy
+ * moment e, at 1 (tau = 1).  A single lambda can cancel both parts only when
+ * omega = 1, so the bracket is split (see feq_general) and each part gets the
+ * coefficient of its own moment:
+ *   lam_s = (1/omega - 1/2)(1/3 - dp0/drho)   traceless part,
+ *   lam_b = (1 - 1/2)(1/3 - dp0/drho)          isotropic part;
+ * at omega = 1 this is the single-lambda form written in Eq. (equilibrium).
+ * lambda_mode 0 takes these values and 1 sets both to 0 (both modes also in
+ * the GPU library).  Two more modes exist only to test the reading on the CPU:
+ * 2 flips both signs (a planted mistake) and 3 is the single-lambda form with
+ * the stress rate, lam_s = lam_b = (1/omega - 1/2)(1/3 - dp0/drho). */
 void orc_feq(const orc_params* p, double rho, double ux, double uy, double omega, double X,
              double dxq, double dyq, double* feq) {
-    double lambda = 0.0;
-    if (p->model == ORC_VDW && p->lambda_mode == 0) {
+    double lam_s = 0.0, lam_b = 0.0;
+    if (p->model == ORC_VDW && p->lambda_mode != 1) {
         double dp0 = p->T / ((1.0 - p->b * rho) * (1.0 - p->b * rho)) - 2.0 * p->a * rho;
-        lambda = (1.0 / omega - 0.5) * (1.0 / 3.0 - dp0);
+        lam_s = (1.0 / omega - 0.5) * (1.0 / 3.0 - dp0);
+        lam_b = (1.0 - 0.5) * (1.0 / 3.0 - dp0);
+        if (p->lambda_mode == 2) {
+            lam_s = -lam_s;
+            lam_b = -lam_b;
+        }
+        if (p->lambda_mode == 3) lam_b = lam_s;
     }
-    feq_general(rho, ux, uy, X, lambda, p->kappa, dxq, dyq, feq);
+    feq_general(rho, ux, uy, X, lam_s, lam_b, p->kappa, dxq, dyq, feq);
 }
 
 /* g^eq of Appendix A with Gamma = 2M/dt. */
@@ -485,6 +515,11 @@ static void compute_stencils(orc_state* s) {
 }
 
 int orc_create(const orc_params* p, const orc_geom* g, const double* init_q, orc_state** out) {
+    return orc_create_flow(p, g, init_q, NULL, NULL, out);
+}
+
+int orc_create_flow(const orc_params* p, const orc_geom* g, const double* init_q, const double* init_ux,
+                    const double* init_uy, orc_state** out) {
     *out = NULL;
     int rc = check_params(p);
     if (rc) return rc;
@@ -495,7 +530,8 @@ int orc_create(const orc_params* p, const orc_geom* g, const double* init_q, orc
         for (int x = 0; x < g->nx; ++x) {
             if (is_solid_xy(g, x, y)) continue;
             double v = init_q[y * g->nx + x];
-            if (!isfinite(v)) {
+            if (!isfinite(v) || (init_ux && !isfinite(init_ux[y * g->nx + x])) ||
+                (init_uy && !isfinite(init_uy[y * g->nx + x]))) {
                 set_err("non-finite initial field");
                 return ORC_EINVAL;
             }
@@ -545,7 +581,8 @@ int orc_create(const orc_params* p, const orc_geom* g, const double* init_q, orc
             s->phi[k] = init_q[k];
             s->q[k] = init_q[k];
         }
-        s->ux[k] = s->uy[k] = 0.0;
+        s->ux[k] = init_ux ? init_ux[k] : 0.0;
+        s->uy[k] = init_uy ? init_uy[k] : 0.0;
     }
     compute_stencils(s);
     for (int k = 0; k < n; ++k) {

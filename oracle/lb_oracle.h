@@ -27,7 +27,9 @@ typedef struct {
     double nu_l, nu_g;   /* kinematic viscosities; vdW uses nu_l (Eq. nu for binary) */
     double wall_grad;    /* prescribed normal gradient of rho/phi at the wall, n into fluid */
     double force_x;      /* uniform body force along x (Guo forcing); 0 in capillary runs */
-    int    lambda_mode;  /* 0: Chapman-Enskog lambda for vdW, 1: lambda = 0 */
+    int    lambda_mode;  /* 0: Chapman-Enskog lambda for vdW (traceless and isotropic
+                            parts of the Galilean term each with the rate of its own
+                            moment), 1: lambda = 0; 2 and 3: test-only variants (orc_feq) */
 } orc_params;
 
 typedef struct {
@@ -44,6 +46,9 @@ int orc_threads(void);   /* OpenMP threads the oracle's loops use */
 /* Build the state at t = 0: f = f^eq, g = g^eq of the initial field init_q
  * (ny*nx, row-major, y major): rho for vdW, phi for binary (rho = 1). */
 int  orc_create(const orc_params* p, const orc_geom* g, const double* init_q, orc_state** out);
+/* The same with an initial velocity field (ny*nx each, NULL = 0): f = f^eq(q, u). */
+int  orc_create_flow(const orc_params* p, const orc_geom* g, const double* init_q,
+                     const double* init_ux, const double* init_uy, orc_state** out);
 void orc_free(orc_state* s);
 int  orc_step(orc_state* s, long nsteps);
 long orc_time(const orc_state* s);

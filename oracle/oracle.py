@@ -99,6 +99,8 @@ def _load():
     lib.orc_threads.restype = C.c_int
     lib.orc_create.argtypes = [C.POINTER(_Params), C.POINTER(_Geom), dp, C.POINTER(C.c_void_p)]
     lib.orc_create.restype = C.c_int
+    lib.orc_create_flow.argtypes = [C.POINTER(_Params), C.POINTER(_Geom), dp, dp, dp, C.POINTER(C.c_void_p)]
+    lib.orc_create_flow.restype = C.c_int
     lib.orc_free.argtypes = [C.c_void_p]
     lib.orc_step.argtypes = [C.c_void_p, C.c_long]
     lib.orc_step.restype = C.c_int
@@ -188,12 +190,21 @@ def collide(p: OracleParams, f, fe, omega, ux, uy, Fx=0.0, Fy=0.0) -> np.ndarray
 class Oracle:
     """One lattice advanced by the FP64 oracle."""
 
-    def __init__(self, params: OracleParams, geom: OracleGeom, init_q: np.ndarray):
+    def __init__(self, params: OracleParams, geom: OracleGeom, init_q: np.ndarray, init_u=None):
+        """init_q: rho (vdW) or phi (binary), (ny, nx); init_u: optional (ux, uy)
+        initial velocity, each (ny, nx) or a scalar (uniform); default at rest."""
         self.params, self.geom = params, geom
-        q = np.ascontiguousarray(init_q, dtype=np.float64).reshape(geom.ny * geom.nx)
+        n = geom.ny * geom.nx
+        q = np.ascontiguousarray(init_q, dtype=np.float64).reshape(n)
         self._p, self._g = params.c(), geom.c()
         h = C.c_void_p()
-        _check(_load().orc_create(C.byref(self._p), C.byref(self._g), _dp(q), C.byref(h)))
+        if init_u is None:
+            _check(_load().orc_create(C.byref(self._p), C.byref(self._g), _dp(q), C.byref(h)))
+        else:
+            ux, uy = (np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), (geom.ny, geom.nx)))
+                      .reshape(n) for v in init_u)
+            _check(_load().orc_create_flow(C.byref(self._p), C.byref(self._g), _dp(q), _dp(ux), _dp(uy),
+                                           C.byref(h)))
         self._h = h
 
     def __del__(self):
