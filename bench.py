@@ -123,6 +123,18 @@ def make_oracle(w):
     return Oracle(p, OracleGeom(**w.geom.asdict()), w.initial_field())
 
 
+def cpu_model() -> str:
+    """Model name of the host CPU (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(w, target_s: float = 15.0):
     """The FP64 oracle on one capillary of the workload, for a bounded number
     of steps (calibrated to about target_s seconds)."""
@@ -138,7 +150,8 @@ def cpu_baseline(w, target_s: float = 15.0):
     dt = time.perf_counter() - t0
     return {"value": fluid * n / dt / 1e6, "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
             "sample": f"capillary {w.name} ({w.geom.nx}x{w.geom.ny}, {fluid} fluid nodes), "
-                      f"{n} steps, {dt:.1f} s"}
+                      f"{n} steps, {dt:.1f} s",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def oracle_next_to_gpu(L, log):

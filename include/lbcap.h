@@ -63,9 +63,13 @@ typedef enum { LB_VDW = 0, LB_BINARY = 1 } lb_model;
  *    with lb_wall_gradient_for_angle.
  *  force_x: uniform body force along x (Guo, Zheng & Shi 2002 forcing in
  *    moment space); acts on fluid nodes that are not boundary nodes.
- *  lambda_mode: 0 uses lambda = (1/omega - 1/2)(1/3 - dp0/drho) in the
- *    Galilean-correction term of Eq. (equilibrium) for vdW; 1 sets lambda = 0.
- *    The binary model always uses lambda = 0.
+ *  lambda_mode: 0 gives the Galilean-correction term of Eq. (equilibrium)
+ *    (vdW) the Chapman-Enskog coefficients of the Appendix A rates: its
+ *    traceless part (1/omega - 1/2)(1/3 - dp0/drho), relaxed with the stresses
+ *    at omega, and its isotropic part (1/2)(1/3 - dp0/drho), relaxed with the
+ *    energy moment at rate 1 (one lambda when omega = 1, as printed); this is
+ *    what keeps a translating interface moving with the fluid.  1 sets
+ *    lambda = 0.  The binary model always uses lambda = 0.
  *  q_mid: level of rho/phi that marks the interface for the filled length;
  *    NaN selects 0 (binary) or the mean of the Maxwell coexistence densities
  *    of p0 (vdW). */
@@ -258,9 +262,19 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg);
 
 /* Autotuner: times the candidate launch configurations on this context's own
  * lattices (each for `trial_steps` steps, state restored afterwards), keeps
- * the fastest and returns it with its time per step in microseconds.
- * The result is cached per (model, tile count class) for later contexts. */
+ * the fastest and returns it with its time per step in microseconds.  The
+ * arithmetic (fp64_arith) is not tuned: candidates keep the context's value.
+ * The shape found is also remembered for this process, per model and size
+ * class (floor(log2) of the number of fluid nodes). */
 lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double* us_per_step);
+
+/* Apply the launch shape last tuned in this process for the context's model
+ * and size class, if any (*found = 1; else 0 and nothing changes).  Only the
+ * shape fields are taken (schedule, tile_rows, chunk_rows,
+ * persist_blocks_per_cu, graph_steps); fp64_arith stays the context's own.
+ * A context never takes a tuned shape by itself: it starts from the default
+ * configuration, so its results do not depend on what was tuned before it. */
+lb_status lb_use_tuned_launch_config(lb_ctx* c, int* found);
 
 /* Average duration (microseconds) of the step kernel over the launches
  * enqueued by the last lb_step / lb_batch_step call, measured with HIP events
@@ -291,6 +305,18 @@ lb_status mlp_get_params(mlp_net* net, float* host, long count);
 lb_status mlp_set_params(mlp_net* net, const float* host, long count);
 /* Forward pass for n rows. */
 lb_status mlp_predict(mlp_net* net, const float* X, int n, float* Y);
+/* Allocation-free forward pass, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same outputs as mlp_predict, from caller-owned
+ * DEVICE arrays X (n x 19) and Y (n x 64, written), enqueued on the network's
+ * stream without synchronising.  No allocation: the hidden activations live
+ * in a static device array of 3 x MLP_NOALLOC_MAX_ROWS x 256 floats (3 MiB)
+ * that each GPU holds until the process ends; n above MLP_NOALLOC_MAX_ROWS is
+ * rejected with LB_EINVAL.  Every call on one GPU uses the same array, so calls
+ * that overlap in time on one GPU (other streams, other threads, other
+ * networks) race and must be serialised by the caller. */
+#define MLP_NOALLOC_MAX_ROWS 1024
+lb_status mlp_predict_device_noalloc(mlp_net* net, const float* X, int n, float* Y);
 /* Mean-squared-error loss and its parameter gradient for n rows (no update);
  * grads has mlp_param_count floats in the mlp_get_params layout. */
 lb_status mlp_loss_grad(mlp_net* net, const float* X, const float* Y, int n, float* loss,

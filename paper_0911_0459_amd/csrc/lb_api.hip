@@ -291,9 +291,13 @@ uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ULL) {
     return h;
 }
 
+// Launch shapes found by lb_autotune, per (model, size class); a context uses
+// one only when its caller asks (lb_use_tuned_launch_config), so that a run's
+// launch shape never depends on what else the process tuned before it.
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, lb_launch_config> g_tune_cache;
 
+// floor(log2(fluid nodes)): the size class of the tuning cache
 int size_class(long long fluid) {
     int c = 0;
     while (fluid > 1) {
@@ -607,11 +611,6 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
         lb_free(c);
         return fail(LB_EDEVICE, "event creation failed");
-    }
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find({c->model, size_class(c->L.fluid)});
-        if (it != g_tune_cache.end()) c->cfg = it->second;
     }
     auto bail = [&](lb_status st) {
         std::string m = g_err;
@@ -1064,6 +1063,26 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
     c->cfg = *cfg;
     drop_graphs(c);
     if (retile) return upload_tiles(c);
+    return LB_OK;
+}
+
+lb_status lb_use_tuned_launch_config(lb_ctx* c, int* found) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (found) *found = 0;
+    lb_launch_config cf = c->cfg;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find({c->model, size_class(c->L.fluid)});
+        if (it == g_tune_cache.end()) return LB_OK;
+        // the shape only: the arithmetic stays the context's own choice
+        cf.tile_rows = it->second.tile_rows;
+        cf.schedule = it->second.schedule;
+        cf.persist_blocks_per_cu = it->second.persist_blocks_per_cu;
+        cf.graph_steps = it->second.graph_steps;
+        cf.chunk_rows = it->second.chunk_rows;
+    }
+    if (lb_status s = lb_set_launch_config(c, &cf)) return s;
+    if (found) *found = 1;
     return LB_OK;
 }
 

@@ -201,20 +201,39 @@ __device__ __forceinline__ R mu_bulk(const CapDev& c, R phi) {
     return (R)c.B * phi * ((phi - (R)c.phib) * (phi + (R)c.phib));
 }
 
+// Coefficients of the Galilean term of the van der Waals equilibrium.  The
+// non-ideal p0 leaves the first-order momentum flux with
+// -(tau - 1/2)(1/3 - dp0/drho)[u_a d_b rho + u_b d_a rho + delta_ab u.grad rho]
+// (Chapman-Enskog), tau the relaxation time of the moments that carry it: the
+// traceless stresses relax at omega, the trace (the energy moment e) at 1
+// (Appendix A rates).  Each part of the bracket gets its own coefficient,
+//   lam = (1/omega - 1/2)(1/3 - dp0/drho),  lam_b = (1/2)(1/3 - dp0/drho),
+// which coincide with the single lambda of Eq. (equilibrium) at omega = 1.
+// inv_omega_mh: 1/omega - 1/2; dp0: dp0/drho at the node.
+template <typename R>
+__device__ __forceinline__ void vdw_lambdas(R inv_omega_mh, R dp0, R& lam, R& lam_b) {
+    const R base = R(1) / R(3) - dp0;
+    lam = inv_omega_mh * base;
+    lam_b = R(0.5) * base;
+}
+
 // MRT collision of one node in moment space (Appendix A rates, Guo source
 // (I - S/2) M F), returning the shifted post-collision populations.
 //   m:   pre-collision moments (rho - rho_ref, j after rest, pxx, pxy)
 //   dX:  X - X_ref, X = p0 - kappa q lap(q) the isotropic part of Eq. (equilibrium)
-//   lam: Galilean-term coefficient; dq: gradient of q; F: body force on this node
+//   lam, lam_b: coefficients of the traceless part and of the isotropic part of
+//        the Galilean term lambda [u_a d_b q + u_b d_a q + delta_ab u.grad q] of
+//        Eq. (equilibrium) (equal in the printed form; see vdw_lambdas)
+//   dq: gradient of q; F: body force on this node
 // LAM = false drops the Galilean terms at compile time (lam must then be 0, as
 // in the binary model) and FORCE = false the forcing terms (F must then be 0);
 // the results are the same, with fewer instructions.
 template <typename R, typename S = R, bool LAM = true, bool FORCE = true>
-__device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX, R lam, R omega,
-                                        R dxq, R dyq, R F, R (&o)[9]) {
+__device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX, R lam, R lam_b,
+                                        R omega, R dxq, R dyq, R F, R (&o)[9]) {
     const R kappa = (R)c.kappa;
     const R u2 = rho * (ux * ux + uy * uy);
-    const R trQ = LAM ? u2 + R(4) * lam * (ux * dxq + uy * dyq) : u2;
+    const R trQ = LAM ? u2 + R(4) * lam_b * (ux * dxq + uy * dyq) : u2;
     const R grad2 = dxq * dxq + dyq * dyq;
     // traceless stresses of the equilibrium and their relaxation in S
     const S sux = (S)ux, suy = (S)uy, sdx = (S)dxq, sdy = (S)dyq, srho = (S)rho, slam = (S)lam;
@@ -374,13 +393,10 @@ __device__ __forceinline__ void step_tile_vdw(const StepArgs& a, int tile, R* qs
     // p0(rho) - p0(rho_ref) = drho [T / ((1 - b rho)(1 - b rho_ref)) - a (rho + rho_ref)]
     const R dX = m.drho * (T * ib * (R)c.ibr - av * (rho + rho_ref)) - kappa * rho * lapq;
     const R omega = (R)c.omega_l;
-    R lam = R(0);
-    if (c.lam_on != 0.f) {
-        const R dp0 = T * ib * ib - R(2) * av * rho;
-        lam = (R(1) / omega - R(0.5)) * (R(1) / R(3) - dp0);
-    }
+    R lam = R(0), lam_b = R(0);
+    if (c.lam_on != 0.f) vdw_lambdas(R(1) / omega - R(0.5), T * ib * ib - R(2) * av * rho, lam, lam_b);
     R o[9];
-    collide(c, m, rho, ux, uy, dX, lam, omega, dxq, dyq, F, o);
+    collide(c, m, rho, ux, uy, dX, lam, lam_b, omega, dxq, dyq, F, o);
     float* __restrict__ fdst = k.dst + c.off_f;
     const long long own_idx = (long long)yw * g.pitch + xw;
 #pragma unroll
@@ -514,7 +530,7 @@ __device__ __forceinline__ void step_tile_bin(const StepArgs& a, int tile, R* ld
     const R nu = nu_g + R(0.5) * (pc + R(1)) * (nu_l - nu_g);
     const R omega = R(2) / (R(6) * nu + R(1));
     R o[9];
-    collide<R, R, false>(c, m, rho, ux, uy, dX, R(0), omega, dxq, dyq, F, o);
+    collide<R, R, false>(c, m, rho, ux, uy, dX, R(0), R(0), omega, dxq, dyq, F, o);
     float* __restrict__ fdst = k.dst + c.off_f;
     const long long own_idx = (long long)yw * g.pitch + xw;
 #pragma unroll

@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
             const float nu = c.nu_g + 0.5f * (pc + 1.f) * (c.nu_l - c.nu_g);
             const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
             CT o[9];
-            collide<CT, ST, false, FORCE>(c, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            collide<CT, ST, false, FORCE>(c, mc, rho_c, ux_cur, uy_cur, dX, CT(0), CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
@@ -558,13 +558,10 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
             const CT ib = recip(CT(1) - (CT)cd.b * rho);
             const CT dX = m.drho * (T * ib * (CT)cd.ibr - av * (rho + rho_ref)) - (CT)cd.kappa * rho * (CT)lapf;
             const CT omega = (CT)cd.omega_l;
-            CT lam = CT(0);
-            if (cd.lam_on != 0.f) {
-                const CT dp0 = T * ib * ib - CT(2) * av * rho;
-                lam = (recip(omega) - CT(0.5)) * (CT(1) / CT(3) - dp0);
-            }
+            CT lam = CT(0), lam_b = CT(0);
+            if (cd.lam_on != 0.f) vdw_lambdas(recip(omega) - CT(0.5), T * ib * ib - CT(2) * av * rho, lam, lam_b);
             CT o[9];
-            collide<CT, CT, true, FORCE>(cd, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
+            collide<CT, CT, true, FORCE>(cd, m, rho, ux, uy, dX, lam, lam_b, omega, (CT)dxf, (CT)dyf, F, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);

@@ -109,12 +109,16 @@ class Workload:
 
 
 def initial_field(geom: Geometry, liquid: float, gas: float, gas_frac: float, seed: int,
-                  amp: float = 1e-3) -> np.ndarray:
-    """Sharp liquid/gas step plus node noise, shape (ny, nx), y major."""
+                  amp: float = 1e-3, l0: int = 0) -> np.ndarray:
+    """Sharp liquid/gas step plus node noise, shape (ny, nx), y major; with
+    l0 > 0 the liquid column already reaches l0 nodes into the tube (the
+    paper's capillary starts at l = 10)."""
     q = np.full((geom.ny, geom.nx), gas, dtype=np.float64)
     if geom.tube_len > 0:
         x_gas_end = int(round(gas_frac * geom.x_in))
         q[:, x_gas_end: geom.x_in] = liquid
+        if l0 > 0:
+            q[geom.y0: geom.y0 + geom.tube_h, geom.x_in: geom.x_in + min(l0, geom.tube_len)] = liquid
     q += node_noise(seed, geom.nx, geom.ny, amp)
     return q
 

@@ -26,6 +26,7 @@ _lib = C.CDLL(LIB)
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_EUNSTABLE, LB_ESTATE = 0, -1, -2, -3, -4, -5
 LB_VDW, LB_BINARY = 0, 1
 LB_HISTORY_CAP = 4096
+MLP_NOALLOC_MAX_ROWS = 1024
 
 
 class LbError(RuntimeError):
@@ -87,6 +88,7 @@ _SIGS = {
     "lb_get_launch_config": (C.c_int, [_vp, C.POINTER(lb_launch_config)]),
     "lb_set_launch_config": (C.c_int, [_vp, C.POINTER(lb_launch_config)]),
     "lb_autotune": (C.c_int, [_vp, C.c_int, C.POINTER(lb_launch_config), _dp]),
+    "lb_use_tuned_launch_config": (C.c_int, [_vp, _ip]),
     "lb_last_step_kernel_us": (C.c_int, [_vp, _dp]),
     "lb_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "lb_meniscus_angle_field": (C.c_int, [_dp, C.POINTER(lb_geometry), C.c_double, C.c_int, _dp, _dp, _dp]),
@@ -97,6 +99,7 @@ _SIGS = {
     "mlp_get_params": (C.c_int, [_vp, _fp, C.c_long]),
     "mlp_set_params": (C.c_int, [_vp, _fp, C.c_long]),
     "mlp_predict": (C.c_int, [_vp, _fp, C.c_int, _fp]),
+    "mlp_predict_device_noalloc": (C.c_int, [_vp, _vp, C.c_int, _vp]),
     "mlp_loss_grad": (C.c_int, [_vp, _fp, _fp, C.c_int, _fp, _fp]),
     "mlp_train": (C.c_int, [_vp, _fp, _fp, C.c_int, C.c_int, C.c_int, C.c_float, C.c_int, _fp]),
 }
@@ -326,6 +329,13 @@ class Lattice:
         _check(_lib.lb_autotune(self._h, trial_steps, C.byref(cfg), C.byref(us)))
         return cfg, us.value
 
+    def use_tuned_launch_config(self) -> bool:
+        """Apply the shape last tuned in this process for this model and size
+        class (the arithmetic stays); False if there is none."""
+        found = C.c_int()
+        _check(_lib.lb_use_tuned_launch_config(self._h, C.byref(found)))
+        return bool(found.value)
+
     # -- checkpoints -----------------------------------------------------------------
     def save(self) -> bytes:
         n = int(_lib.lb_checkpoint_bytes(self._h))
@@ -371,6 +381,19 @@ class MLP:
         Y = np.zeros((X.shape[0], self.N_OUT), dtype=np.float32)
         _check(_lib.mlp_predict(self._h, _f32(X), X.shape[0], _f32(Y)))
         return Y
+
+    def predict_device_noalloc(self, X, Y) -> None:
+        """Forward pass from device tensor X (n x 19, float32, contiguous) into
+        device tensor Y (n x 64), n <= MLP_NOALLOC_MAX_ROWS, without any device
+        allocation; enqueued on the network's stream, not synchronised."""
+        for t, cols in ((X, self.N_IN), (Y, self.N_OUT)):
+            if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 4 and t.is_contiguous()
+                    and t.dim() == 2 and t.shape[1] == cols):
+                raise LbError(LB_EINVAL, "X and Y must be contiguous float32 device tensors (n x 19, n x 64)")
+        if X.shape[0] != Y.shape[0]:
+            raise LbError(LB_EINVAL, "X and Y row counts differ")
+        _check(_lib.mlp_predict_device_noalloc(self._h, C.c_void_p(X.data_ptr()), int(X.shape[0]),
+                                               C.c_void_p(Y.data_ptr())))
 
     def loss_grad(self, X: np.ndarray, Y: np.ndarray):
         X = np.ascontiguousarray(X, dtype=np.float32)

@@ -77,6 +77,23 @@ def test_binary_capillary_1e4_steps(L):
     assert np.abs(lg - lo).max() <= 0.5
 
 
+def test_binary_capillary_1024x128_1e4_steps(L):
+    """The binary capillary at its real size: 1024x128, tube H=40 and length
+    768, ratio 10, 60 degrees, seed 2, default launch shape, 10^4 steps against
+    the oracle, the filled length compared every 500 steps."""
+    w = I.binary_capillary_1024x128()
+    print(f"binary 1024x128 1e4: GPU run", flush=True)
+    gpu, lg = gpu_run(L, w, 10_000, sample_every=500)
+    print(f"binary 1024x128 1e4: oracle run", flush=True)
+    orc, lo = run_oracle(w, 10_000, sample_every=500)
+    drho, dphi, du = field_errors(w, gpu, orc)
+    print(f"binary 1024x128 1e4: max rel drho {drho:.3e}, max dphi {dphi:.3e}, du {du:.3e}, "
+          f"max dl {np.abs(lg - lo).max():.3e}, l_oracle {lo[0]:.2f} -> {lo[-1]:.2f}")
+    assert drho <= 1e-4 and dphi <= 1e-4
+    assert np.abs(lg - lo).max() <= 0.5
+    assert lo[-1] > lo[0] + 5.0          # the liquid is filling the tube
+
+
 # ---- tight short-run parity across tiles, tails and launch shapes --------------
 SHAPES = [
     dict(tile_rows=1, schedule=0, persist_blocks_per_cu=4, graph_steps=0, fp64_arith=0),
@@ -395,15 +412,43 @@ def test_autotune_keeps_state(L):
     assert cfg.schedule in (0, 1, 2, 3, 4) and us > 0
     assert a.t == 40
     a.step(60)
-    # a new lattice of this size class starts from the tuned shape: replay a's history
+    # a new lattice starts from the default shape, and takes the tuned one only
+    # when asked: replay a's history
     b = L.Lattice(p, g, w.initial_field())
-    assert b.launch_config().asdict() == cfg.asdict()
-    b.set_launch_config(**cfg0.asdict())
+    assert b.launch_config().asdict() == cfg0.asdict()
     b.step(40)
-    b.set_launch_config(**cfg.asdict())
+    assert b.use_tuned_launch_config()
+    assert b.launch_config().asdict() == cfg.asdict()
     b.step(60)
     for x, y in zip(a.moments(), b.moments()):
         assert np.array_equal(x, y)
+
+
+def test_results_do_not_depend_on_earlier_tuning(L):
+    """Two identical runs give the same bits whatever was tuned in between:
+    a tuning run in FP32 arithmetic on a lattice of the same size class leaves
+    the next context at the default shape and arithmetic, and applying the
+    tuned shape keeps the context's own arithmetic."""
+    w = small_binary(nx=260, ny=56, H=20, seed=61)
+    p = L.params_from_workload(w, wall_grad=oracle_wall_grad(w))
+    g = L.geometry_from_workload(w)
+    first = L.Lattice(p, g, w.initial_field())
+    default = first.launch_config().asdict()
+    first.step(120)
+    ref = first.moments()
+    first.close()
+    other = L.Lattice(p, g, w.initial_field())
+    other.set_launch_config(**dict(default, fp64_arith=0))
+    other.autotune(trial_steps=4)
+    other.close()
+    again = L.Lattice(p, g, w.initial_field())
+    assert again.launch_config().asdict() == default
+    again.step(120)
+    for x, y in zip(ref, again.moments()):
+        assert np.array_equal(x, y)
+    assert again.use_tuned_launch_config()
+    assert again.launch_config().fp64_arith == default["fp64_arith"]
+    again.close()
 
 
 def test_every_strip_chunking_fits_one_capillary(L):
