@@ -235,17 +235,22 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    that supplies the two neighbour columns), so that no stored cache line is
  *    shared between workgroups.  The same arithmetic as 3, compiled apart:
  *    the results agree to the last bits (vdW bitwise, binary within 3e-7).
+ *    5 (van der Waals model only) the strips of 4, each launch advancing two
+ *    time steps: the sweep reads the populations once with a halo of three
+ *    nodes, keeps the intermediate step in LDS and writes the second step, so
+ *    that the populations cross HBM once per two steps; an odd step count
+ *    ends with one launch of schedule 4.  The same arithmetic per step.
  *    0..2 tiles of 64 x tile_rows nodes with the order field recomputed on a
  *    halo: 0 one workgroup per tile in table order, 1 tiles grouped per XCD,
  *    2 persistent workgroups (persist_blocks_per_cu x 256 CUs) striding the table.
  *  tile_rows: rows per tile for schedules 0..2 (1, 2, 4 or 8).
- *  chunk_rows: target rows per strip chunk for schedules 3 and 4 (0, or 4..4096;
+ *  chunk_rows: target rows per strip chunk for schedules 3..5 (0, or 4..4096;
  *    default 8): each strip column is cut into chunks of about that height that
  *    start an even number of rows apart, so that the results do not depend on it.
  *    From 12 rows on, the last rows of the last columns of each XCD's run go to
  *    short chunks (a quarter of the height, at least 4 rows) that end the step.
- *  graph_steps: steps captured per HIP graph (even, >= 2; 0 = no graphs).
- *  fp64_arith: 1 evaluates the collision in FP64 (schedules 3, 4; schedules 0..2
+ *  graph_steps: time steps captured per HIP graph (even, >= 2; 0 = no graphs).
+ *  fp64_arith: 1 evaluates the collision in FP64 (schedules 3..5; schedules 0..2
  *    then compute the whole step in FP64), 0 in FP32.  The stored state is FP32
  *    either way (same memory traffic). */
 typedef struct {

@@ -27,6 +27,7 @@
 #include "lb_strip.h"
 #include "lb_strip_table.h"
 #include "lb_wide.h"
+#include "lb_wide2.h"
 #include "lb_thermo.h"
 
 using namespace lbk;
@@ -356,7 +357,10 @@ void drop_graphs(lb_ctx* c) {
 }
 
 // output columns per strip of the row-sweep schedules (3: one wavefront, 4: a workgroup)
-int strip_width(const lb_launch_config& cfg) { return cfg.schedule == 4 ? WIDE_OUT : STRIP_OUT; }
+int strip_width(const lb_launch_config& cfg) { return cfg.schedule >= 4 ? WIDE_OUT : STRIP_OUT; }
+
+// time steps one launch of the step kernel advances (schedule 5: two per sweep)
+int steps_per_launch(const lb_launch_config& cfg) { return cfg.schedule == 5 ? 2 : 1; }
 
 lb_status upload_tiles(lb_ctx* c) {
     std::vector<TileDev> tiles;
@@ -414,10 +418,12 @@ int grid_of(const lb_ctx* c) {
 constexpr size_t STRIP_BIN_LDS_PAD = 6 * 1024;
 
 template <int MODEL, typename MT, typename CT, typename ST, bool FORCE>
-void launch_strip_f(lb_ctx* c, const StripArgs& a, int grid) {
-    const bool wide = c->cfg.schedule == 4;
+void launch_strip_f(lb_ctx* c, const StripArgs& a, int grid, bool fused) {
+    const bool wide = c->cfg.schedule >= 4;
     if constexpr (MODEL == 0) {
-        if (wide)
+        if (fused)
+            hipLaunchKernelGGL((lb_wide2_vdw<CT, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
+        else if (wide)
             hipLaunchKernelGGL((lb_wide_vdw<CT, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
         else
             hipLaunchKernelGGL((lb_strip_vdw<CT, FORCE>), dim3(grid), dim3(SW), 0, c->stream, a);
@@ -432,17 +438,19 @@ void launch_strip_f(lb_ctx* c, const StripArgs& a, int grid) {
 
 // without a body force anywhere in the batch the forcing terms are compiled out
 template <int MODEL, typename MT, typename CT, typename ST = CT>
-void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid) {
+void launch_strip_t(lb_ctx* c, const StripArgs& a, int grid, bool fused) {
     if (c->any_force)
-        launch_strip_f<MODEL, MT, CT, ST, true>(c, a, grid);
+        launch_strip_f<MODEL, MT, CT, ST, true>(c, a, grid, fused);
     else
-        launch_strip_f<MODEL, MT, CT, ST, false>(c, a, grid);
+        launch_strip_f<MODEL, MT, CT, ST, false>(c, a, grid, fused);
 }
 
-// Enqueue one step (or the initialisation when init is true) from arena cur.
-void enqueue_step(lb_ctx* c, bool init) {
+// Enqueue one step (or the initialisation when init is true) from arena cur;
+// fused: two steps in one sweep (schedule 5), else a single step (schedule 5
+// then takes the single-step wide strips, for odd step counts).
+void enqueue_step(lb_ctx* c, bool init, bool fused = false) {
     if (c->ntiles == 0) return;
-    if (!init && (c->cfg.schedule == 3 || c->cfg.schedule == 4)) {
+    if (!init && c->cfg.schedule >= 3) {
         if (c->nstrips == 0) return;
         StripArgs a;
         a.caps = c->d_caps;
@@ -460,15 +468,15 @@ void enqueue_step(lb_ctx* c, bool init) {
         const int grid = 8 * longest;
         if (c->model == LB_VDW) {
             if (c->cfg.fp64_arith)
-                launch_strip_t<0, double, double>(c, a, grid);
+                launch_strip_t<0, double, double>(c, a, grid, fused);
             else
-                launch_strip_t<0, float, float>(c, a, grid);
+                launch_strip_t<0, float, float>(c, a, grid, fused);
         } else {
             // the collision's non-shear part in FP64 (the shear relaxation is exact enough in FP32)
             if (c->cfg.fp64_arith)
-                launch_strip_t<1, float, double, float>(c, a, grid);
+                launch_strip_t<1, float, double, float>(c, a, grid, fused);
             else
-                launch_strip_t<1, float, float, float>(c, a, grid);
+                launch_strip_t<1, float, float, float>(c, a, grid, fused);
         }
         return;
     }
@@ -496,30 +504,41 @@ void enqueue_step(lb_ctx* c, bool init) {
     }
 }
 
+// Every launch reads arena cur and writes the other one, so each flips cur,
+// whether it advances one time step or two.
 lb_status run_steps(lb_ctx* c, long n) {
     const int K = c->cfg.graph_steps;
+    const int spl = steps_per_launch(c->cfg);
     if (K >= 2 && (K % 2) == 0 && n >= K && c->ntiles > 0) {
-        if (!c->gexec[c->cur]) {
-            const int p = c->cur;
-            HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-            for (int s = 0; s < K; ++s) {
-                enqueue_step(c, false);
-                c->cur ^= 1;
-            }
-            hipGraph_t gr = nullptr;
-            HIP_TRY(hipStreamEndCapture(c->stream, &gr));
-            c->graph[p] = gr;
-            HIP_TRY(hipGraphInstantiate(&c->gexec[p], gr, nullptr, nullptr, 0));
-            // capture does not execute: parity is back where it was (K even)
-        }
+        const int launches = K / spl;   // K is even
         while (n >= K) {
+            if (!c->gexec[c->cur]) {
+                // a graph per starting arena; capture does not execute
+                const int p = c->cur;
+                HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+                for (int s = 0; s < launches; ++s) {
+                    enqueue_step(c, false, spl == 2);
+                    c->cur ^= 1;
+                }
+                c->cur = p;
+                hipGraph_t gr = nullptr;
+                HIP_TRY(hipStreamEndCapture(c->stream, &gr));
+                c->graph[p] = gr;
+                HIP_TRY(hipGraphInstantiate(&c->gexec[p], gr, nullptr, nullptr, 0));
+            }
             HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
+            c->cur ^= launches & 1;
             c->t += K;
             n -= K;
         }
     }
-    for (long s = 0; s < n; ++s) {
-        enqueue_step(c, false);
+    for (; n >= spl; n -= spl) {
+        enqueue_step(c, false, spl == 2);
+        c->cur ^= 1;
+        c->t += spl;
+    }
+    if (n > 0) {   // an odd step of a two-step schedule
+        enqueue_step(c, false, false);
         c->cur ^= 1;
         c->t += 1;
     }
@@ -1049,7 +1068,9 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
     if (!c || !cfg) return fail(LB_EINVAL, "null argument");
     const int r = cfg->tile_rows;
     if (r != 1 && r != 2 && r != 4 && r != 8) return fail(LB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
-    if (cfg->schedule < 0 || cfg->schedule > 4) return fail(LB_EINVAL, "schedule must be 0, 1, 2, 3 or 4");
+    if (cfg->schedule < 0 || cfg->schedule > 5) return fail(LB_EINVAL, "schedule must be 0, 1, 2, 3, 4 or 5");
+    if (cfg->schedule == 5 && c->model != LB_VDW)
+        return fail(LB_EINVAL, "schedule 5 (two steps per sweep) is built for the van der Waals model only");
     if (cfg->schedule == 2 && (cfg->persist_blocks_per_cu < 1 || cfg->persist_blocks_per_cu > 32))
         return fail(LB_EINVAL, "persistent workgroups per CU must be in 1..32");
     if (cfg->graph_steps != 0 && (cfg->graph_steps < 2 || cfg->graph_steps % 2 != 0 || cfg->graph_steps > 4096))
@@ -1106,6 +1127,8 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     const int ar = orig.fp64_arith;   // the arithmetic is a choice of the caller, not tuned
     for (int ch : {6, 8, 12, 16, 32}) cand.push_back({orig.tile_rows, 3, 4, 0, ar, ch});
     for (int ch : {8, 12, 16, 32}) cand.push_back({orig.tile_rows, 4, 4, 0, ar, ch});
+    if (c->model == LB_VDW)
+        for (int ch : {8, 12, 16, 24, 32}) cand.push_back({orig.tile_rows, 5, 4, 0, ar, ch});
     for (int r : {4, 8}) {
         cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
         cand.push_back({r, 2, 4, 0, ar, orig.chunk_rows});

@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             const float nu = cd.nu_g + 0.5f * (pc + 1.f) * (cd.nu_l - cd.nu_g);
             const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
             CT o[9];
-            collide<CT, ST, false, FORCE>(cd, mc, rho_c, ux_cur, uy_cur, dX, CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            collide<CT, ST, false, FORCE>(cd, mc, rho_c, ux_cur, uy_cur, dX, CT(0), CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
@@ -280,6 +280,41 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
 }
 
 // ---- van der Waals model ---------------------------------------------------------
+// Collision of one fluid node of the van der Waals model from the FP32 moments
+// of its pulled populations and the stencils of rho (the vdW row sweeps share
+// it, so they compile the same arithmetic): thermodynamics of Sec. 2, the
+// Galilean coefficients of vdw_lambdas, MRT relaxation in arithmetic type CT.
+// sm: the node's solid-neighbour bits (boundary nodes take no body force).
+template <typename CT, bool FORCE>
+__device__ __forceinline__ void vdw_node_collide(const CapDev& c, const Mom<float>& mom, unsigned sm, float dxf,
+                                                 float dyf, float lapf, CT (&o)[9]) {
+    // constants of the FP64 part, converted where used (see uniform_opaque)
+    CapDev cd = c;
+    uniform_opaque(cd.Fx);
+    uniform_opaque(cd.rho_ref);
+    uniform_opaque(cd.T);
+    uniform_opaque(cd.a);
+    uniform_opaque(cd.b);
+    uniform_opaque(cd.ibr);
+    uniform_opaque(cd.kappa);
+    uniform_opaque(cd.omega_l);
+    const bool bnd = sm != 0u;
+    const CT F = (FORCE && !bnd) ? (CT)cd.Fx : CT(0);
+    const Mom<CT> m{(CT)mom.drho, (CT)mom.jx, (CT)mom.jy, (CT)mom.pxx, (CT)mom.pxy};
+    const CT rho_ref = (CT)cd.rho_ref;
+    const CT rho = rho_ref + m.drho;
+    const CT inv_rho = recip(rho);
+    const CT ux = (FORCE ? m.jx + CT(0.5) * F : m.jx) * inv_rho;
+    const CT uy = m.jy * inv_rho;
+    const CT T = (CT)cd.T, av = (CT)cd.a;
+    const CT ib = recip(CT(1) - (CT)cd.b * rho);
+    const CT dX = m.drho * (T * ib * (CT)cd.ibr - av * (rho + rho_ref)) - (CT)cd.kappa * rho * (CT)lapf;
+    const CT omega = (CT)cd.omega_l;
+    CT lam = CT(0), lam_b = CT(0);
+    if (cd.lam_on != 0.f) vdw_lambdas(recip(omega) - CT(0.5), T * ib * ib - CT(2) * av * rho, lam, lam_b);
+    collide<CT, CT, true, FORCE>(cd, m, rho, ux, uy, dX, lam, lam_b, omega, (CT)dxf, (CT)dyf, F, o);
+}
+
 template <typename CT, bool FORCE = true>
 __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
     const int si = strip_index(a);
@@ -351,36 +386,9 @@ __global__ void __launch_bounds__(WIDE_THREADS) lb_wide_vdw(StripArgs a) {
         lds_barrier();
         if (out_col && fl_cur) {
             float dxf, dyf, lapf;
-            // constants of the FP64 part, converted where used (see uniform_opaque)
-            CapDev cd = c;
-            uniform_opaque(cd.Fx);
-            uniform_opaque(cd.rho_ref);
-            uniform_opaque(cd.T);
-            uniform_opaque(cd.a);
-            uniform_opaque(cd.b);
-            uniform_opaque(cd.ibr);
-            uniform_opaque(cd.kappa);
-            uniform_opaque(cd.omega_l);
             stencil3(Q[s4(yr - 1)], Q[s4(yr)], Q[s4(yr + 1)], uj, sm_cur, G2, dxf, dyf, lapf);
-            const bool bnd = sm_cur != 0u;
-            const CT F = (FORCE && !bnd) ? (CT)cd.Fx : CT(0);
-            const Mom<CT> m{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
-            const CT rho_ref = (CT)cd.rho_ref;
-            const CT rho = rho_ref + m.drho;
-            const CT inv_rho = recip(rho);
-            const CT ux = (FORCE ? m.jx + CT(0.5) * F : m.jx) * inv_rho;
-            const CT uy = m.jy * inv_rho;
-            const CT T = (CT)cd.T, av = (CT)cd.a;
-            const CT ib = recip(CT(1) - (CT)cd.b * rho);
-            const CT dX = m.drho * (T * ib * (CT)cd.ibr - av * (rho + rho_ref)) - (CT)cd.kappa * rho * (CT)lapf;
-            const CT omega = (CT)cd.omega_l;
-            CT lam = CT(0);
-            if (cd.lam_on != 0.f) {
-                const CT dp0 = T * ib * ib - CT(2) * av * rho;
-                lam = (recip(omega) - CT(0.5)) * (CT(1) / CT(3) - dp0);
-            }
             CT o[9];
-            collide<CT, CT, true, FORCE>(cd, m, rho, ux, uy, dX, lam, omega, (CT)dxf, (CT)dyf, F, o);
+            vdw_node_collide<CT, FORCE>(c, mom_cur, sm_cur, dxf, dyf, lapf, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);

@@ -553,3 +553,96 @@ def test_graph_replays_equal_direct_launches(L):
         for x, y in zip(rep.moments(), ref):
             assert np.array_equal(x, y)
         rep.close()
+
+
+# ---- two time steps per sweep (schedule 5, van der Waals) ----------------------
+FUSED_GEOMS = {
+    "ragged150x37": I.Geometry(nx=150, ny=37, x_in=53, tube_len=97, tube_h=13, y0=11),
+    "wide700x45": I.Geometry(nx=700, ny=45, x_in=250, tube_len=450, tube_h=17, y0=14),
+    "ends520x41": I.Geometry(nx=520, ny=41, x_in=150, tube_len=280, tube_h=15, y0=13),
+    "periodic5x3": I.Geometry(nx=5, ny=3),
+}
+
+
+@pytest.mark.parametrize("name", list(FUSED_GEOMS))
+def test_fused_vdw_equals_single_steps_and_oracle(L, name):
+    """Schedule 5 (two steps per sweep, the intermediate step in LDS) against
+    single-step wide strips: bitwise equal, whatever the chunking (0, 5, 12, 24
+    rows), graphs or direct launches, with an odd step count (the last step a
+    single-step launch); and against the oracle."""
+    g = FUSED_GEOMS[name]
+    w = I.Workload(f"vdw_fused_{name}", "vdw", g, 0, 0, seed=71, nu_l=0.13, nu_g=0.13, wall_grad=-0.1,
+                   liquid=4.5, gas=2.6, **I.VDW_CONSTS)
+    init = None
+    if name == "periodic5x3":
+        init = np.array([[4.5, 4.4, 3.0, 2.6, 2.7], [4.5, 4.2, 3.1, 2.6, 2.8], [4.3, 4.5, 2.9, 2.7, 2.6]])
+    steps = 201
+    print(f"fused vdw {name}: single-step reference", flush=True)
+    ref, _ = gpu_run(L, w, steps, cfg=dict(schedule=4, chunk_rows=8, graph_steps=0, fp64_arith=1), init=init)
+    for cfg in (dict(schedule=5, chunk_rows=0, graph_steps=64), dict(schedule=5, chunk_rows=5, graph_steps=0),
+                dict(schedule=5, chunk_rows=12, graph_steps=2), dict(schedule=5, chunk_rows=24, graph_steps=64)):
+        print(f"fused vdw {name}: {cfg}", flush=True)
+        got, _ = gpu_run(L, w, steps, cfg=dict(cfg, fp64_arith=1), init=init)
+        gap = max(float(np.abs(x - y).max()) for x, y in zip(ref, got))
+        assert gap == 0.0, (cfg, gap)
+    orc, _ = run_oracle(w, steps, init=init)
+    drho, _, du = field_errors(w, ref, orc)
+    assert drho < 2e-5 and du < 1e-6, (drho, du)
+    got32, _ = gpu_run(L, w, steps, cfg=dict(schedule=5, chunk_rows=12, graph_steps=64, fp64_arith=0), init=init)
+    drho, _, du = field_errors(w, got32, orc)
+    assert drho < 2e-5 and du < 1e-6, ("fp32", drho, du)
+
+
+def test_fused_vdw_graph_replays_and_sampling(L):
+    """Schedule 5 run from graphs (64 steps = 32 fused launches per replay)
+    interleaved with direct launches, odd step counts and host reads, and a
+    batch sampled every 25 steps (odd): bitwise the single-step run, and the
+    same filled-length history."""
+    w = I.vdw_capillary_256x64()
+    p = L.params_from_workload(w)
+    g = L.geometry_from_workload(w)
+    direct = L.Lattice(p, g, w.initial_field())
+    direct.set_launch_config(schedule=4, chunk_rows=8, graph_steps=0)
+    direct.step(300)
+    ref = direct.moments()
+    direct.close()
+    rep = L.Lattice(p, g, w.initial_field())
+    rep.set_launch_config(schedule=5, chunk_rows=12, graph_steps=64)
+    for n in (64, 70, 64, 1, 101):
+        rep.step(n)
+        rep.interface_length()
+        rep.moments()
+    assert rep.t == 300
+    for x, y in zip(rep.moments(), ref):
+        assert np.array_equal(x, y)
+    rep.close()
+    hists = []
+    for shape in (dict(schedule=4, chunk_rows=8), dict(schedule=5, chunk_rows=16)):
+        b = L.Lattice([p, p], [g, g], [w.initial_field(), w.initial_field()])
+        b.set_launch_config(**shape, graph_steps=64)
+        b.step(275, sample_every=25)
+        hists.append([b.l_history(k) for k in range(2)])
+        b.close()
+    for (t0, h0), (t1, h1) in zip(*hists):
+        assert list(t0) == list(t1) == list(range(25, 276, 25))
+        assert np.array_equal(h0, h1)
+
+
+def test_vdw_capillary_256x64_1e4_steps_fused(L):
+    """The liquid-gas 10^4-step gate (256x64, H=20, tau 0.8) with two steps per sweep."""
+    w = I.vdw_capillary_256x64()
+    gpu, lg = gpu_run(L, w, 10_000, sample_every=500, cfg=dict(schedule=5, chunk_rows=12))
+    orc, lo = run_oracle(w, 10_000, sample_every=500)
+    drho, _, du = field_errors(w, gpu, orc)
+    print(f"vdw fused 1e4: max rel drho {drho:.3e}, max du {du:.3e}, max dl {np.abs(lg - lo).max():.3e}")
+    assert drho <= 1e-4
+    assert np.abs(lg - lo).max() <= 0.5
+
+
+def test_fused_schedule_is_refused_for_the_binary_model(L):
+    w = small_binary(nx=130, ny=40, H=12)
+    lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), w.initial_field())
+    with pytest.raises(L.LbError) as e:
+        lat.set_launch_config(schedule=5, chunk_rows=8)
+    assert e.value.code == L.LB_EINVAL
+    lat.close()
