@@ -16,6 +16,8 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -183,6 +185,17 @@ __global__ void mlp_gather(const float* __restrict__ X, const float* __restrict_
     for (int c = threadIdx.x; c < cols_y; c += blockDim.x) Yb[(long)r * cols_y + c] = Y[src * cols_y + c];
 }
 
+// ---- allocation-free inference scratch ------------------------------------------
+// Activations of mlp_predict_device_noalloc: one buffer for the pre-activations
+// the forward pass writes but inference does not read, and two that the hidden
+// activations alternate between, each MLP_NOALLOC_MAX_ROWS x 256 floats
+// (3 MiB in all).  Every GPU that runs the library holds its own copy until
+// the process ends; host code addresses it only through the pointer that
+// hipGetSymbolAddress returned for that GPU (noalloc_scratch below).
+constexpr int SCRATCH_BUFS = 3;
+constexpr long SCRATCH_BUF = (long)MLP_NOALLOC_MAX_ROWS * WMAX;
+static __device__ __align__(256) float scratch[SCRATCH_BUFS * SCRATCH_BUF];
+
 // ---- host side -----------------------------------------------------------------
 
 long param_count() {
@@ -219,6 +232,7 @@ double uniform01(uint64_t seed, uint64_t i) {
 }  // namespace
 
 struct mlp_net {
+    int device = -1;           // the GPU the parameters live on
     hipStream_t stream = nullptr;
     float* P = nullptr;        // parameters, mlp_get_params layout
     float* G = nullptr;        // gradients, same layout
@@ -278,32 +292,65 @@ lb_status gemm(hipStream_t s, const GemmArgs& g) {
     return LB_OK;
 }
 
-// Forward pass of `rows` rows of act[0]; output in z[NLAYER-1].
-lb_status forward(mlp_net* n, int rows) {
+// Forward pass of `rows` rows with parameters P on stream s: layer l reads
+// in[l] and writes its pre-activation to z[l] and (hidden layers) its GELU to
+// in[l + 1]; z[NLAYER-1] receives the output.
+lb_status forward_bufs(hipStream_t s, const float* P, int rows, const float* const (&in)[NLAYER],
+                       float* const (&z)[NLAYER]) {
     for (int l = 0; l < NLAYER; ++l) {
-        const int in = DIMS[l], out = DIMS[l + 1];
+        const int ni = DIMS[l], no = DIMS[l + 1];
         GemmArgs g{};
         g.M = rows;
-        g.N = out;
-        g.K = in;
-        g.A = n->act[l];
-        g.sam = in;
+        g.N = no;
+        g.K = ni;
+        g.A = in[l];
+        g.sam = ni;
         g.sak = 1;
-        g.B = n->P + w_off(l);   // B(k, j) = W[j][k]
+        g.B = P + w_off(l);   // B(k, j) = W[j][k]
         g.sbk = 1;
-        g.sbn = in;
-        g.C = n->z[l];
-        g.ldc = out;
-        g.bias = n->P + b_off(l);
+        g.sbn = ni;
+        g.C = z[l];
+        g.ldc = no;
+        g.bias = P + b_off(l);
         lb_status st;
         if (l + 1 < NLAYER) {
-            g.H = n->act[l + 1];
-            st = gemm<EPI_BIAS_GELU>(n->stream, g);
+            g.H = const_cast<float*>(in[l + 1]);
+            st = gemm<EPI_BIAS_GELU>(s, g);
         } else {
-            st = gemm<EPI_BIAS>(n->stream, g);
+            st = gemm<EPI_BIAS>(s, g);
         }
         if (st) return st;
     }
+    return LB_OK;
+}
+
+// Forward pass of `rows` rows of act[0]; output in z[NLAYER-1].
+lb_status forward(mlp_net* n, int rows) {
+    const float* const in[NLAYER] = {n->act[0], n->act[1], n->act[2], n->act[3]};
+    float* const z[NLAYER] = {n->z[0], n->z[1], n->z[2], n->z[3]};
+    return forward_bufs(n->stream, n->P, rows, in, z);
+}
+
+// Device address of this GPU's copy of `scratch`, resolved once per device
+// (with that device current) by hipGetSymbolAddress: the array's name in host
+// code is a host-side stand-in, not a device address.
+std::mutex g_scratch_mu;
+std::map<int, float*> g_scratch_ptr;
+
+lb_status noalloc_scratch(int device, float** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return LB_OK;
+    }
+    int cur = -1;
+    MLP_TRY(hipGetDevice(&cur));
+    if (cur != device) return lbk::set_error(LB_ESTATE, "the network's device is not the current device");
+    void* p = nullptr;
+    MLP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[device] = (float*)p;
+    *out = (float*)p;
     return LB_OK;
 }
 
@@ -384,6 +431,10 @@ lb_status mlp_init(mlp_net** out, int seed, void* hip_stream) {
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return lbk::set_error(LB_EDEVICE, "no HIP device");
     mlp_net* n = new mlp_net();
     n->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&n->device) != hipSuccess) {
+        delete n;
+        return lbk::set_error(LB_EDEVICE, "no current HIP device");
+    }
     const long np = param_count();
     auto bail = [&](lb_status st) {
         mlp_free(n);
@@ -403,6 +454,9 @@ lb_status mlp_init(mlp_net** out, int seed, void* hip_stream) {
         hipMemset(n->G, 0, sizeof(float) * np) != hipSuccess || hipMemset(n->Mo, 0, sizeof(float) * np) != hipSuccess ||
         hipMemset(n->Vo, 0, sizeof(float) * np) != hipSuccess)
         return bail(lbk::set_error(LB_EDEVICE, "network initialisation failed"));
+    // set-up of the allocation-free inference path on this device
+    float* sc = nullptr;
+    if (lb_status st = noalloc_scratch(n->device, &sc)) return bail(st);
     *out = n;
     return LB_OK;
 }
@@ -455,6 +509,24 @@ lb_status mlp_predict(mlp_net* n, const float* X, int rows, float* Y) {
                            n->stream));
     MLP_TRY(hipStreamSynchronize(n->stream));
     return LB_OK;
+}
+
+lb_status mlp_predict_device_noalloc(mlp_net* n, const float* dX, int rows, float* dY) {
+    if (lb_status st = check_net(n)) return st;
+    if (rows < 0 || rows > MLP_NOALLOC_MAX_ROWS)
+        return lbk::set_error(LB_EINVAL, "mlp_predict_device_noalloc: rows must be in 0..MLP_NOALLOC_MAX_ROWS (1024)");
+    if (rows > 0 && (!dX || !dY)) return lbk::set_error(LB_EINVAL, "null device arrays");
+    if (rows == 0) return LB_OK;
+    float* sc = nullptr;
+    if (lb_status st = noalloc_scratch(n->device, &sc)) return st;
+    // layer inputs: X, then the hidden activations alternating between the
+    // second and third scratch buffers; pre-activations of the hidden layers
+    // into the first (not read), the output straight into Y
+    float* const a = sc + SCRATCH_BUF;
+    float* const b = sc + 2 * SCRATCH_BUF;
+    const float* const in[NLAYER] = {dX, a, b, a};
+    float* const z[NLAYER] = {sc, sc, sc, dY};
+    return forward_bufs(n->stream, n->P, rows, in, z);
 }
 
 lb_status mlp_loss_grad(mlp_net* n, const float* X, const float* Y, int rows, float* loss, float* grads) {
