@@ -194,11 +194,19 @@ def oracle_next_to_gpu(L, log):
     return {"oracle_threads": oracle.threads(), "configs": out}
 
 
-def sweep_compare(works, log):
-    """Wall time of the 256-capillary sweep: plain sequential runs (estimated
-    from 1000 timed steps of each), one batched run, and the batched run with
-    learned early stopping; the true error of every accepted tail is taken
-    from the full batched run."""
+def plain_subset(works, n: int = 16):
+    """n capillaries spanning the size range: every (len/n)-th by fluid-node count."""
+    order = sorted(range(len(works)), key=lambda k: works[k].geom.fluid_count())
+    return [order[(2 * j + 1) * len(order) // (2 * n)] for j in range(n)]
+
+
+def sweep_compare(works, log, plain_full: bool = False):
+    """Wall time of the 256-capillary sweep: plain sequential runs, one batched
+    run, and the batched run with learned early stopping; the true error of
+    every accepted tail is taken from the full batched run.  The plain time is
+    measured, every capillary alone for all its steps, with plain_full;
+    otherwise it is estimated from 1000 timed steps of each run, and 16 runs
+    spanning the size range are also run in full to check the estimate."""
     import numpy as np
     from paper_0911_0459_amd import surrogate as S
     net_path = os.path.join(S.DATA_DIR, "surrogate_net.npz")
@@ -208,7 +216,19 @@ def sweep_compare(works, log):
     full = S.run_sweep(works, T, None, log=log)
     sur = S.Surrogate.load(net_path)
     early = S.run_sweep(works, T, sur, log=log)
-    plain = S.plain_sequential_estimate(works, T, log=log)
+    if plain_full:
+        meas = S.plain_sequential(works, T, log=log)
+        plain_s, note = meas["measured_s"], "measured: every capillary alone for all its steps"
+        check = None
+    else:
+        est = S.plain_sequential_estimate(works, T, log=log)
+        plain_s = est["estimated_s"]
+        note = f"estimated from {est['sample_steps']} timed steps of each run"
+        idx = plain_subset(works)
+        meas = S.plain_sequential([works[k] for k in idx], T, log=log)
+        est_sub = float(sum(est["per_run_s"][k] for k in idx))
+        check = {"runs": len(idx), "measured_s": round(meas["measured_s"], 2), "estimated_s": round(est_sub, 2),
+                 "measured_over_estimated": round(meas["measured_s"] / est_sub, 4)}
     hist = np.stack(full["hist"])
     p = S.RunParams.of(works)
     truth = S.interp_history(hist, T, S.out_times(T))
@@ -219,11 +239,12 @@ def sweep_compare(works, log):
     acc_wb = ev_wb["accept"]
     return {
         "capillaries": len(works), "steps_per_run": T,
-        "plain_sequential_s": round(plain["estimated_s"], 1),
-        "plain_sequential_note": f"estimated from {plain['sample_steps']} timed steps of each run",
+        "plain_sequential_s": round(plain_s, 1),
+        "plain_sequential_note": note,
+        "plain_subset_full_runs": check,
         "batched_s": round(full["wall_s"], 1),
         "batched_surrogate_s": round(early["wall_s"], 1),
-        "speedup_batched_surrogate_vs_plain": round(plain["estimated_s"] / early["wall_s"], 2),
+        "speedup_batched_surrogate_vs_plain": round(plain_s / early["wall_s"], 2),
         "speedup_batched_surrogate_vs_batched": round(full["wall_s"] / early["wall_s"], 2),
         "accepted": int(acc.sum()),
         "accepted_true_err_max": round(float(err[acc].max()), 5) if acc.any() else None,
@@ -250,6 +271,9 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=-1, help="steps per HIP graph (0: direct launches)")
     ap.add_argument("--copy-probe", action="store_true", help="time the plain copy kernel only")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep wall-time comparison")
+    ap.add_argument("--plain-full", action="store_true",
+                    help="measure the plain sequential sweep in full (every capillary alone for all its steps, "
+                         "about 5 minutes) instead of estimating it")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="time the FP64 oracle next to the GPU on the three single-lattice configurations only")
     args = ap.parse_args()
@@ -338,7 +362,7 @@ def main():
     del lat
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.workload == "sweep" and not args.no_sweep:
-        out["sweep"] = sweep_compare(works, log)
+        out["sweep"] = sweep_compare(works, log, plain_full=args.plain_full)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(works[0])
     print(json.dumps(out))

@@ -163,6 +163,46 @@ lb_status lb_meniscus_angle_field(const double* q, const lb_geometry* g, double 
 lb_status lb_meniscus_angle(lb_ctx* c, int cap, int edge_rows, double* theta_deg, double* radius,
                             double* apex_x);
 
+/* Flow along the tube (Sec. 2.2, Fig. 3).  From host fields (ny x nx,
+ * row-major) q (rho for vdW, phi for binary: locates the meniscus), rho and u_x:
+ *  u_centre (caller-owned, tube_len doubles, may be NULL): u_x on the tube
+ *    centreline (mean of the two middle rows for even H) at x_in .. x_in+tube_len-1;
+ *  out->l: the filled length, as lb_interface_length, from q and q_mid;
+ *  out->rho_liquid, u_liquid: mean density and mass-weighted mean x velocity
+ *    sum(rho u_x)/sum(rho) of the channel rows from x_in + margin to the
+ *    meniscus minus margin (the liquid column; liquid_cols columns);
+ *  out->rho_gas, u_gas: the same from the meniscus plus margin to the tube's
+ *    end minus margin (the gas ahead; gas_cols columns);
+ *  out->condensation_liquid_side = rho_liquid (v_meniscus - u_liquid) and
+ *  out->condensation_gas_side = rho_gas (v_meniscus - u_gas): the mass that
+ *    crosses the moving meniscus per unit time and width, seen from either
+ *    side (positive: the gas condenses); equal for a steady interface.
+ *    v_meniscus is the meniscus speed dl/dt, e.g. from two filled lengths.
+ * lb_tube_flow reads capillary cap of a context with its own q_mid
+ * (synchronises).  LB_EINVAL: no tube, margin < 0, non-finite q_mid or
+ * v_meniscus. */
+typedef struct {
+    double l;
+    double rho_liquid, u_liquid;
+    double rho_gas, u_gas;
+    double condensation_liquid_side, condensation_gas_side;
+    int liquid_cols, gas_cols;
+} lb_tube_flow_stats;
+lb_status lb_tube_flow_field(const double* q, const double* rho, const double* ux, const lb_geometry* g,
+                             double q_mid, int margin, double v_meniscus, double* u_centre, lb_tube_flow_stats* out);
+lb_status lb_tube_flow(lb_ctx* c, int cap, int margin, double v_meniscus, double* u_centre,
+                       lb_tube_flow_stats* out);
+
+/* Filled length l(t) by the capillary balance of Eq. 1 - 3 with the viscous
+ * drag of the liquid column (dynamic viscosity eta_l) and of the gas column of
+ * length L - l ahead of it (eta_g): the solution of
+ *   (eta_l - eta_g) (l^2 - l0^2) / 2 + eta_g L (l - l0) = gamma H cos(theta) t / 6
+ * continuous with l(0) = l0 (Sec. 2.2, Fig. "10", dashed and dotted lines);
+ * eta_g = 0 is Washburn's law, Eq. 3.  Host arithmetic, no device.
+ * LB_EINVAL for t < 0, l0 outside [0, L], H <= 0, eta_l <= 0, eta_g < 0. */
+lb_status lb_washburn_length(double t, double l0, double H, double L, double gamma, double cos_theta,
+                             double eta_l, double eta_g, double* l);
+
 /* Wall gradient that gives the equilibrium contact angle theta_deg by Young's
  * law (Eq. Young) with the surface tensions of the Cahn construction for a
  * surface energy linear in the wall value of rho/phi (Sec. 2.2, Fig. 2).

@@ -15,6 +15,7 @@
 // angle theta with cos(theta) = (H/2) / R, measured through the liquid (the
 // liquid fills from the inlet side): positive when the centre lies on the gas
 // side (a wetting meniscus), negative otherwise.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -78,5 +79,99 @@ extern "C" lb_status lb_meniscus_angle_field(const double* q, const lb_geometry*
     if (theta_deg) *theta_deg = std::acos(cos_t) * (180.0 / M_PI);
     if (radius) *radius = R;
     if (apex_x) *apex_x = apex;
+    return LB_OK;
+}
+
+// ---- flow along the tube (Sec. 2.2, Fig. 3) ----------------------------------
+// The liquid column is the set of channel rows from x_in + margin to the
+// meniscus (the filled length) minus margin, the gas ahead of it the rows from
+// the meniscus plus margin to the tube's end minus margin.  Over each region
+// the mean density and the mass-weighted mean x velocity sum(rho u_x) /
+// sum(rho) are formed; with the meniscus speed v the rates at which mass
+// crosses the interface, per unit width, are rho (v - u) on either side: the
+// rate of condensation when positive.  In a steady moving interface the two
+// sides carry the same rate (mass conservation across the interface).
+extern "C" lb_status lb_tube_flow_field(const double* q, const double* rho, const double* ux, const lb_geometry* g,
+                                         double q_mid, int margin, double v_meniscus, double* u_centre,
+                                         lb_tube_flow_stats* out) {
+    if (!q || !rho || !ux || !g || !out) return lbk::set_error(LB_EINVAL, "null argument");
+    if (g->tube_len <= 0 || g->tube_h <= 0) return lbk::set_error(LB_EINVAL, "the geometry has no tube");
+    if (margin < 0 || !std::isfinite(q_mid) || !std::isfinite(v_meniscus))
+        return lbk::set_error(LB_EINVAL, "margin must be >= 0, q_mid and v_meniscus finite");
+    const int nx = g->nx, H = g->tube_h;
+    const int ya = (H % 2 == 0) ? g->y0 + H / 2 - 1 : g->y0 + (H - 1) / 2;
+    const int yb = (H % 2 == 0) ? g->y0 + H / 2 : ya;
+    auto at = [&](const double* f, int x, int y) { return f[(size_t)y * nx + x]; };
+    // filled length from the centreline order field (the definition of lb_interface_length)
+    double l = g->tube_len;
+    for (int k = 0; k < g->tube_len; ++k) {
+        const int x = g->x_in + k;
+        const double qc = 0.5 * (at(q, x, ya) + at(q, x, yb));
+        if (qc < q_mid) {
+            if (k == 0) {
+                l = 0.0;
+            } else {
+                const double qp = 0.5 * (at(q, x - 1, ya) + at(q, x - 1, yb));
+                l = (k - 1) + (qp - q_mid) / (qp - qc);
+            }
+            break;
+        }
+    }
+    if (u_centre)
+        for (int k = 0; k < g->tube_len; ++k) {
+            const int x = g->x_in + k;
+            u_centre[k] = 0.5 * (at(ux, x, ya) + at(ux, x, yb));
+        }
+    auto region = [&](int x0, int x1, double& rho_m, double& u_m, int& cols) {
+        double m = 0.0, p = 0.0;
+        long n = 0;
+        for (int x = x0; x < x1; ++x)
+            for (int y = g->y0; y < g->y0 + H; ++y) {
+                m += at(rho, x, y);
+                p += at(rho, x, y) * at(ux, x, y);
+                ++n;
+            }
+        cols = std::max(0, x1 - x0);
+        rho_m = n > 0 ? m / (double)n : 0.0;
+        u_m = m > 0.0 ? p / m : 0.0;
+    };
+    const int xm = g->x_in + (int)std::floor(l);
+    int cl = 0, cg = 0;
+    region(g->x_in + margin, std::min(xm - margin, g->x_in + g->tube_len), out->rho_liquid, out->u_liquid, cl);
+    region(std::max(xm + 1 + margin, g->x_in), g->x_in + g->tube_len - margin, out->rho_gas, out->u_gas, cg);
+    out->l = l;
+    out->liquid_cols = cl;
+    out->gas_cols = cg;
+    out->condensation_liquid_side = cl > 0 ? out->rho_liquid * (v_meniscus - out->u_liquid) : 0.0;
+    out->condensation_gas_side = cg > 0 ? out->rho_gas * (v_meniscus - out->u_gas) : 0.0;
+    return LB_OK;
+}
+
+// ---- Washburn's law with the drag of the gas (Eq. 1 - 3) ---------------------
+// The capillary pressure 2 gamma cos(theta) / H drives the liquid column of
+// length l and the gas column of length L - l ahead of it, each in Poiseuille
+// flow (Eq. 1: dp/dx = -12 eta v / H^2), at the speed v = dl/dt:
+//   2 gamma cos(theta) / H = 12 v (eta_l l + eta_g (L - l)) / H^2,
+// whose integral from l(0) = l0 is
+//   (eta_l - eta_g) (l^2 - l0^2) / 2 + eta_g L (l - l0) = gamma H cos(theta) t / 6.
+// eta_g = 0 gives Eq. 3, l^2 = l0^2 + gamma H cos(theta) t / (3 eta_l).
+extern "C" lb_status lb_washburn_length(double t, double l0, double H, double L, double gamma, double cos_theta,
+                                         double eta_l, double eta_g, double* l) {
+    if (!l) return lbk::set_error(LB_EINVAL, "null argument");
+    if (!(t >= 0.0) || !(l0 >= 0.0) || !(H > 0.0) || !(L >= l0) || !(eta_l > 0.0) || !(eta_g >= 0.0) ||
+        !std::isfinite(gamma) || !std::isfinite(cos_theta) || !std::isfinite(t))
+        return lbk::set_error(LB_EINVAL, "need t >= 0, 0 <= l0 <= L, H > 0, eta_l > 0, eta_g >= 0");
+    const double a = 0.5 * (eta_l - eta_g), b = eta_g * L;
+    const double c = a * l0 * l0 + b * l0 + gamma * H * cos_theta * t / 6.0;   // a l^2 + b l = c
+    double x;
+    if (a == 0.0) {
+        x = c / b;
+    } else {
+        const double disc = b * b + 4.0 * a * c;
+        if (!(disc >= 0.0)) return lbk::set_error(LB_EINVAL, "no real filled length (gas column stalls the flow)");
+        // the root continuous with l0, without cancellation
+        x = 2.0 * c / (b + std::sqrt(disc));
+    }
+    *l = x;
     return LB_OK;
 }

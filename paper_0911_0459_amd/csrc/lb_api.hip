@@ -918,6 +918,19 @@ lb_status lb_meniscus_angle(lb_ctx* c, int cap, int edge_rows, double* theta_deg
     return lb_meniscus_angle_field(q, &g, (double)c->L.caps[cap].q_mid, edge_rows, theta_deg, radius, apex_x);
 }
 
+lb_status lb_tube_flow(lb_ctx* c, int cap, int margin, double v_meniscus, double* u_centre, lb_tube_flow_stats* out) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (lb_status s = cap_index(c, cap)) return s;
+    const lb_geometry& g = c->G[cap];
+    if (g.tube_len <= 0) return fail(LB_EINVAL, "no tube in this geometry");
+    const size_t n = (size_t)g.nx * g.ny;
+    std::vector<double> rho(n), ux(n), phi(n);
+    if (lb_status s = host_moments(c, cap, rho.data(), ux.data(), nullptr, phi.data())) return s;
+    const double* q = c->model == LB_BINARY ? phi.data() : rho.data();
+    return lb_tube_flow_field(q, rho.data(), ux.data(), &g, (double)c->L.caps[cap].q_mid, margin, v_meniscus,
+                              u_centre, out);
+}
+
 lb_status lb_batch_l_history(lb_ctx* c, int cap, double* l, long* steps, int max_samples, int* n_samples) {
     if (lb_status s = check_ctx(c)) return s;
     if (lb_status s = cap_index(c, cap)) return s;

@@ -468,6 +468,43 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
 }
 
 // ---- van der Waals model ---------------------------------------------------------
+// Collision of one fluid node of the van der Waals model from the FP32 moments
+// of its pulled populations and the stencils of rho (every vdW row sweep calls
+// it, so they compile the same arithmetic): thermodynamics of Sec. 2, the
+// Galilean coefficients of vdw_lambdas, MRT relaxation with the non-shear part
+// in arithmetic type CT and the shear relaxation in FP32 (as for the binary
+// model).  sm: the node's solid-neighbour bits (boundary nodes take no body
+// force).
+template <typename CT, bool FORCE>
+__device__ __forceinline__ void vdw_node_collide(const CapDev& c, const Mom<float>& mom, unsigned sm, float dxf,
+                                                 float dyf, float lapf, CT (&o)[9]) {
+    // constants of the FP64 part, converted where used (see uniform_opaque)
+    CapDev cd = c;
+    uniform_opaque(cd.Fx);
+    uniform_opaque(cd.rho_ref);
+    uniform_opaque(cd.T);
+    uniform_opaque(cd.a);
+    uniform_opaque(cd.b);
+    uniform_opaque(cd.ibr);
+    uniform_opaque(cd.kappa);
+    uniform_opaque(cd.omega_l);
+    const bool bnd = sm != 0u;
+    const CT F = (FORCE && !bnd) ? (CT)cd.Fx : CT(0);
+    const Mom<CT> m{(CT)mom.drho, (CT)mom.jx, (CT)mom.jy, (CT)mom.pxx, (CT)mom.pxy};
+    const CT rho_ref = (CT)cd.rho_ref;
+    const CT rho = rho_ref + m.drho;
+    const CT inv_rho = recip(rho);
+    const CT ux = (FORCE ? m.jx + CT(0.5) * F : m.jx) * inv_rho;
+    const CT uy = m.jy * inv_rho;
+    const CT T = (CT)cd.T, av = (CT)cd.a;
+    const CT ib = recip(CT(1) - (CT)cd.b * rho);
+    const CT dX = m.drho * (T * ib * (CT)cd.ibr - av * (rho + rho_ref)) - (CT)cd.kappa * rho * (CT)lapf;
+    const CT omega = (CT)cd.omega_l;
+    CT lam = CT(0), lam_b = CT(0);
+    if (cd.lam_on != 0.f) vdw_lambdas(recip(omega) - CT(0.5), T * ib * ib - CT(2) * av * rho, lam, lam_b);
+    collide<CT, float, true, FORCE>(cd, m, rho, ux, uy, dX, lam, lam_b, omega, (CT)dxf, (CT)dyf, F, o);
+}
+
 template <typename CT, bool FORCE = true>
 __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
     const int si = strip_index(a);
@@ -535,33 +572,9 @@ __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
         wave_sync();
         if (out_col && fl_cur) {
             float dxf, dyf, lapf;
-            // constants of the FP64 part, converted where used (see uniform_opaque)
-            CapDev cd = c;
-            uniform_opaque(cd.Fx);
-            uniform_opaque(cd.rho_ref);
-            uniform_opaque(cd.T);
-            uniform_opaque(cd.a);
-            uniform_opaque(cd.b);
-            uniform_opaque(cd.ibr);
-            uniform_opaque(cd.kappa);
-            uniform_opaque(cd.omega_l);
             stencil3(Q[r3(-1)], Q[r3(0)], Q[r3(1)], k, sm_cur, G2, dxf, dyf, lapf);
-            const bool bnd = sm_cur != 0u;
-            const CT F = (FORCE && !bnd) ? (CT)cd.Fx : CT(0);
-            const Mom<CT> m{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
-            const CT rho_ref = (CT)cd.rho_ref;
-            const CT rho = rho_ref + m.drho;
-            const CT inv_rho = recip(rho);
-            const CT ux = (FORCE ? m.jx + CT(0.5) * F : m.jx) * inv_rho;
-            const CT uy = m.jy * inv_rho;
-            const CT T = (CT)cd.T, av = (CT)cd.a;
-            const CT ib = recip(CT(1) - (CT)cd.b * rho);
-            const CT dX = m.drho * (T * ib * (CT)cd.ibr - av * (rho + rho_ref)) - (CT)cd.kappa * rho * (CT)lapf;
-            const CT omega = (CT)cd.omega_l;
-            CT lam = CT(0), lam_b = CT(0);
-            if (cd.lam_on != 0.f) vdw_lambdas(recip(omega) - CT(0.5), T * ib * ib - CT(2) * av * rho, lam, lam_b);
             CT o[9];
-            collide<CT, CT, true, FORCE>(cd, m, rho, ux, uy, dX, lam, lam_b, omega, (CT)dxf, (CT)dyf, F, o);
+            vdw_node_collide<CT, FORCE>(c, mom_cur, sm_cur, dxf, dyf, lapf, o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);

@@ -93,6 +93,10 @@ _SIGS = {
     "lb_stream_copy": (C.c_int, [_vp, _vp, C.c_size_t, _vp]),
     "lb_meniscus_angle_field": (C.c_int, [_dp, C.POINTER(lb_geometry), C.c_double, C.c_int, _dp, _dp, _dp]),
     "lb_meniscus_angle": (C.c_int, [_vp, C.c_int, C.c_int, _dp, _dp, _dp]),
+    "lb_tube_flow_field": (C.c_int, [_dp, _dp, _dp, C.POINTER(lb_geometry), C.c_double, C.c_int, C.c_double, _dp,
+                                     _vp]),
+    "lb_tube_flow": (C.c_int, [_vp, C.c_int, C.c_int, C.c_double, _dp, _vp]),
+    "lb_washburn_length": (C.c_int, [C.c_double] * 8 + [_dp]),
     "mlp_init": (C.c_int, [C.POINTER(_vp), C.c_int, _vp]),
     "mlp_free": (None, [_vp]),
     "mlp_param_count": (C.c_long, [_vp]),
@@ -188,6 +192,37 @@ def lb_meniscus_angle_field(q: np.ndarray, g: lb_geometry, q_mid: float, edge_ro
     _check(_lib.lb_meniscus_angle_field(_d(q), C.byref(g), float(q_mid), int(edge_rows), C.byref(th),
                                         C.byref(R), C.byref(ax)))
     return th.value, R.value, ax.value
+
+
+class lb_tube_flow_stats(C.Structure):
+    _fields_ = [("l", C.c_double), ("rho_liquid", C.c_double), ("u_liquid", C.c_double), ("rho_gas", C.c_double),
+                ("u_gas", C.c_double), ("condensation_liquid_side", C.c_double),
+                ("condensation_gas_side", C.c_double), ("liquid_cols", C.c_int), ("gas_cols", C.c_int)]
+
+    def asdict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+def lb_tube_flow_field(q: np.ndarray, rho: np.ndarray, ux: np.ndarray, g: lb_geometry, q_mid: float,
+                       margin: int = 3, v_meniscus: float = 0.0):
+    """(lb_tube_flow_stats, centreline u_x over the tube) of host fields (ny x nx)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (q, rho, ux)]
+    if any(a.size != g.nx * g.ny for a in arrs):
+        raise LbError(LB_EINVAL, "field size does not match the geometry")
+    out, line = lb_tube_flow_stats(), np.zeros(max(g.tube_len, 0))
+    _check(_lib.lb_tube_flow_field(*[_d(a) for a in arrs], C.byref(g), float(q_mid), int(margin),
+                                   float(v_meniscus), _d(line), C.byref(out)))
+    return out, line
+
+
+def lb_washburn_length(t: float, l0: float, H: float, L: float, gamma: float, cos_theta: float, eta_l: float,
+                       eta_g: float = 0.0) -> float:
+    """Filled length of the capillary balance with liquid and gas drag
+    (eta_g = 0: Washburn's law, Eq. 3)."""
+    out = C.c_double()
+    _check(_lib.lb_washburn_length(float(t), float(l0), float(H), float(L), float(gamma), float(cos_theta),
+                                   float(eta_l), float(eta_g), C.byref(out)))
+    return out.value
 
 
 def lb_state_bytes(p: lb_params, g: lb_geometry) -> int:
@@ -302,6 +337,13 @@ class Lattice:
         th, R, ax = C.c_double(), C.c_double(), C.c_double()
         _check(_lib.lb_meniscus_angle(self._h, cap, int(edge_rows), C.byref(th), C.byref(R), C.byref(ax)))
         return th.value, R.value, ax.value
+
+    def tube_flow(self, cap: int = 0, margin: int = 3, v_meniscus: float = 0.0):
+        """(lb_tube_flow_stats, centreline u_x over the tube) of capillary cap (Fig. 3)."""
+        out = lb_tube_flow_stats()
+        line = np.zeros(self.geoms[cap].tube_len)
+        _check(_lib.lb_tube_flow(self._h, cap, int(margin), float(v_meniscus), _d(line), C.byref(out)))
+        return out, line
 
     def retire(self, cap: int):
         _check(_lib.lb_batch_retire(self._h, cap))

@@ -440,13 +440,36 @@ def run_sweep(works, T: int, sur: "Surrogate | None" = None, log=None, chunk: in
     return out
 
 
+def plain_sequential(works, T: int, log=None) -> dict:
+    """Measured time of running the capillaries one after another, each alone
+    for all T steps (tuned launch shape, graph replays, l sampled as in the
+    sweep): the stepping time of every run, setup and tuning excluded as in
+    run_sweep."""
+    import torch
+    from . import lbcap as L
+    per_run = []
+    for i, w in enumerate(works):
+        lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), w.initial_field())
+        lat.autotune(trial_steps=10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.step(T, sample_every=T // N_SAMPLES)
+        torch.cuda.synchronize()
+        per_run.append(time.perf_counter() - t0)
+        lat.check()
+        lat.close()
+        if log and (i % 16 == 15 or i + 1 == len(works)):
+            log(f"  plain (full runs): {i + 1} of {len(works)} runs, {sum(per_run):.1f} s")
+    return {"measured_s": float(sum(per_run)), "per_run_s": per_run, "steps": T}
+
+
 def plain_sequential_estimate(works, T: int, sample_steps: int = 1000, log=None) -> dict:
     """Time of running the capillaries one after another (each alone, tuned
     launch shape, graph replays), from sample_steps timed steps of each run,
     scaled to T steps."""
     import torch
     from . import lbcap as L
-    total, sampled = 0.0, 0.0
+    total, sampled, per_run = 0.0, 0.0, []
     for i, w in enumerate(works):
         lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), w.initial_field())
         lat.autotune(trial_steps=10)
@@ -458,7 +481,8 @@ def plain_sequential_estimate(works, T: int, sample_steps: int = 1000, log=None)
         dt = time.perf_counter() - t0
         sampled += dt
         total += dt * T / sample_steps
+        per_run.append(dt * T / sample_steps)
         lat.close()
         if log and i % 64 == 63:
             log(f"  plain: {i + 1} runs sampled")
-    return {"estimated_s": total, "sampled_s": sampled, "sample_steps": sample_steps}
+    return {"estimated_s": total, "sampled_s": sampled, "sample_steps": sample_steps, "per_run_s": per_run}

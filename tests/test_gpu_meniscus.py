@@ -157,40 +157,86 @@ def test_mobility_parity_with_oracle(L, gamma):
     assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6
 
 
-def test_liquid_gas_filling_is_driven_by_condensation(L):
-    """The paper's liquid-gas capillary (Sec. 2.2, Fig. 3 and Fig. 10): 700 x 40
-    fluid rows, x-periodic, a wetting tube of length 350 (walls at -0.144,
-    60 degrees) between y-periodic reservoirs, nu = 1/6, started with l = 10.
-    After 50000 steps the gas ahead of the meniscus flows back towards it, the
-    meniscus advances faster than the liquid behind it flows (the difference
-    condenses at the interface), and the filled length exceeds Washburn's law
-    (Eq. 3) and its version with gas drag."""
+def _paper_vdw_capillary():
+    """The liquid-gas capillary of Sec. 2.2 (Fig. 3, Fig. 10): 700 x 40 fluid
+    rows, x-periodic, a wetting tube of length 350 (walls at -0.144, 60
+    degrees) between y-periodic reservoirs, nu = 1/6, started with l = 10."""
     g = I.Geometry(nx=700, ny=42, x_in=175, tube_len=350, tube_h=40, y0=1)
     w = I.Workload("vdw_700x40", "vdw", g, 0, 0, 7, nu_l=1 / 6, nu_g=1 / 6, theta_deg=60.0, wall_grad=-0.144,
                    liquid=4.54, gas=2.59, **I.VDW_CONSTS)
-    q = w.initial_field()
-    q[g.y0:g.y0 + g.tube_h, g.x_in:g.x_in + 10] = 4.54
+    return g, w, I.initial_field(g, 4.54, 2.59, 0.5, 7, l0=10)
+
+
+def _tube_stats_twin(g, q, rho, ux, q_mid, margin, v):
+    """The test's own statistics of Fig. 3 from fields (the twin of the
+    library's lb_tube_flow_field): filled length on the centreline, mass-
+    weighted x velocity of the liquid column and of the gas ahead of it."""
+    ya, yb = g.y0 + g.tube_h // 2 - 1, g.y0 + g.tube_h // 2
+    qc = 0.5 * (q[ya, g.x_in:g.x_in + g.tube_len] + q[yb, g.x_in:g.x_in + g.tube_len])
+    k = int(np.argmax(qc < q_mid))
+    l = (k - 1) + (qc[k - 1] - q_mid) / (qc[k - 1] - qc[k])
+    xm = g.x_in + int(math.floor(l))
+    rows = slice(g.y0, g.y0 + g.tube_h)
+    liq, gas = slice(g.x_in + margin, xm - margin), slice(xm + 1 + margin, g.x_in + g.tube_len - margin)
+    u_l = (rho[rows, liq] * ux[rows, liq]).sum() / rho[rows, liq].sum()
+    u_g = (rho[rows, gas] * ux[rows, gas]).sum() / rho[rows, gas].sum()
+    return l, u_l, u_g, rho[rows, liq].mean() * (v - u_l), rho[rows, gas].mean() * (v - u_g)
+
+
+def test_liquid_gas_tube_flow_matches_oracle(L):
+    """The Fig. 3 diagnostics at the paper's exact geometry, 2000 steps after
+    the start: the library's centreline u_x(x) over the whole tube equals the
+    oracle's element by element (1e-6, the short-run bar on u), and its filled
+    length, liquid and gas velocities and condensation rates equal the test's
+    own statistics of the oracle's fields."""
+    g, w, q = _paper_vdw_capillary()
+    lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), q)
+    lat.step(2000)
+    stats, line = lat.tube_flow(margin=3, v_meniscus=1e-3)
+    lat.close()
+    (rho_o, ux_o, _, _), _ = run_oracle(w, 2000, init=q)
+    ya, yb = g.y0 + g.tube_h // 2 - 1, g.y0 + g.tube_h // 2
+    line_o = 0.5 * (ux_o[ya, g.x_in:g.x_in + g.tube_len] + ux_o[yb, g.x_in:g.x_in + g.tube_len])
+    print(f"700x40 vdW, 2000 steps: max |u_x centreline - oracle| {np.abs(line - line_o).max():.2e}, "
+          f"l {stats.l:.3f}, u_liquid {stats.u_liquid:.3e}, u_gas {stats.u_gas:.3e}")
+    assert np.abs(line - line_o).max() < 1e-6
+    rl, rg = P.vdw_maxwell()
+    l_o, ul_o, ug_o, cl_o, cg_o = _tube_stats_twin(g, rho_o, rho_o, ux_o, 0.5 * (rl + rg), 3, 1e-3)
+    assert abs(stats.l - l_o) < 1e-3
+    assert abs(stats.u_liquid - ul_o) < 1e-6 and abs(stats.u_gas - ug_o) < 1e-6
+    assert abs(stats.condensation_liquid_side - cl_o) < 1e-5 and abs(stats.condensation_gas_side - cg_o) < 1e-5
+
+
+def test_liquid_gas_filling_is_driven_by_condensation(L):
+    """The paper's liquid-gas capillary after 50000 steps (Sec. 2.2): the gas
+    ahead of the meniscus flows back towards it (Fig. 3), the meniscus
+    advances faster than the liquid behind it flows, so that gas condenses at
+    the interface (the rate seen from the liquid side and from the gas side
+    agree), and the filled length exceeds both Washburn's law (Eq. 3) and the
+    balance with the drag of the gas, which is slower still (Fig. "10")."""
+    g, w, q = _paper_vdw_capillary()
     lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), q)
     lat.step(45_000)
     l0 = lat.interface_length()[0]
     lat.step(5_000)
     l1 = lat.interface_length()[0]
-    rho, ux, uy, _ = lat.moments()
-    lat.close()
-    x_m = g.x_in + int(l1)
-    rows = slice(g.y0, g.y0 + g.tube_h)
-    gas_ahead = ux[g.y0 + g.tube_h // 2, x_m + 3:x_m + 40].mean()
-    liquid_flux = (rho[rows, g.x_in + 5:x_m - 3] * ux[rows, g.x_in + 5:x_m - 3]).sum(axis=0).mean()
-    liquid_mass = rho[rows, g.x_in + 5:x_m - 3].sum(axis=0).mean()
-    u_liquid = liquid_flux / liquid_mass               # mean liquid velocity over the cross-section
     v_meniscus = (l1 - l0) / 5_000.0
-    assert gas_ahead < 0.0 < u_liquid
-    assert v_meniscus > 1.5 * u_liquid
-    # Washburn (Eq. 3) from l = 10: l^2 = 100 + H gamma cos(theta) t / (3 eta_l), eta_l = rho_l nu
-    from oracle import physics as P
+    stats, line = lat.tube_flow(margin=3, v_meniscus=v_meniscus)
+    lat.close()
     rl, rg = P.vdw_maxwell()
-    gamma, t = P.vdw_tension(), 50_000.0
-    l_w = math.sqrt(100.0 + g.tube_h * gamma * 0.5 * t / (3.0 * rl / 6.0))
+    gamma, t, cos_t = P.vdw_tension(), 50_000.0, 0.5
+    l_w = L.lb_washburn_length(t, 10.0, g.tube_h, g.tube_len, gamma, cos_t, rl / 6.0, 0.0)
+    l_wg = L.lb_washburn_length(t, 10.0, g.tube_h, g.tube_len, gamma, cos_t, rl / 6.0, rg / 6.0)
+    print(f"700x40 vdW, 50000 steps: l {l1:.2f} (Washburn {l_w:.2f}, with gas drag {l_wg:.2f}), "
+          f"v_meniscus {v_meniscus:.3e}, u_liquid {stats.u_liquid:.3e}, u_gas {stats.u_gas:.3e}, "
+          f"condensation {stats.condensation_liquid_side:.3e} / {stats.condensation_gas_side:.3e}")
+    x_m = int(stats.l)
+    assert line[x_m + 3:x_m + 40].mean() < 0.0 < stats.u_liquid
+    assert stats.u_gas < 0.0
+    assert v_meniscus > 1.5 * stats.u_liquid
+    assert stats.condensation_liquid_side > 0.0 and stats.condensation_gas_side > 0.0
+    assert abs(stats.condensation_liquid_side / stats.condensation_gas_side - 1.0) < 0.25
+    assert l_wg < l_w
     assert l1 > 1.2 * l_w
 
 
