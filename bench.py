@@ -34,7 +34,7 @@ BYTES_PER_LUP = {"vdw": 72, "binary": 80}   # read + write of every stored FP32 
 
 
 # the step kernels and the strip table that shapes their traffic
-KERNEL_SOURCES = ("lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_strip_table.h", "lb_wide.h", "lb_wide2.h")
+KERNEL_SOURCES = ("lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_strip_table.h", "lb_wide.h", "lb_wide2.h", "lb_wmom.h")
 
 
 def kernel_source_hash() -> str:
@@ -327,8 +327,8 @@ def main():
     mlups = fluid * args.steps / elapsed / 1e6
     bpl = BYTES_PER_LUP[model]
     achieved = bpl * fluid / (us_kernel * 1e-6) / 1e9 if us_kernel > 0 else None
-    kname = ({3: "lb_strip_", 4: "lb_wide_", 5: "lb_wide2_"}[cfg.schedule] + ("bin" if model == "binary" else "vdw")
-             if cfg.schedule in (3, 4, 5) else f"lb_step_kernel_{model}_{cfg.tile_rows}")
+    kname = ({3: "lb_strip_", 4: "lb_wide_", 5: "lb_wide2_", 6: "lb_wmom_"}[cfg.schedule] + ("bin" if model == "binary" else "vdw")
+             if cfg.schedule in (3, 4, 5, 6) else f"lb_step_kernel_{model}_{cfg.tile_rows}")
     traffic = traffic_from_profiles(kname, args.workload, cfg.asdict())
     config.update({"model": model, "fluid_nodes": fluid, "launch": cfg.asdict(), "bytes_per_lup": bpl})
     out = {

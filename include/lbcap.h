@@ -218,7 +218,9 @@ lb_status lb_vdw_coexistence(const lb_params* p, double* rho_l, double* rho_g);
 /* Checkpoint: bytes needed, save into / restore from a caller-owned host
  * buffer.  The image holds the populations, the step count and a hash of the
  * parameters and geometry; lb_load refuses an image of another setup
- * (LB_EINVAL).  Resuming is bitwise identical to not stopping. */
+ * (LB_EINVAL).  Resuming is bitwise identical to not stopping.  The image
+ * records the storage of schedule 6 or of the others; an image of the other
+ * storage is converted on load (then equal to rounding). */
 size_t    lb_checkpoint_bytes(const lb_ctx* c);
 lb_status lb_save(lb_ctx* c, void* host_buf, size_t bytes);
 lb_status lb_load(lb_ctx* c, const void* host_buf, size_t bytes);
@@ -280,17 +282,27 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    nodes, keeps the intermediate step in LDS and writes the second step, so
  *    that the populations cross HBM once per two steps; an odd step count
  *    ends with one launch of schedule 4.  The same arithmetic per step.
+ *    6 (binary model only) the strips of 4 over a stored state of seven FP32
+ *    planes instead of nine populations: with the rates of Appendix A the
+ *    post-collision populations of a node follow from rho - rho_ref, j*, the
+ *    common parts of the axis and of the diagonal populations, pxx* and pxy*,
+ *    so a step moves 32 instead of 40 bytes per node (phi included).  The
+ *    sweep rebuilds the populations of each row once, into LDS, and pulls
+ *    from there.  Setting this schedule converts the stored state in place
+ *    (both buffers); leaving it converts back.  Results agree with schedule 4
+ *    to rounding (the populations are rounded to FP32 after the rebuild
+ *    instead of before the store).
  *    0..2 tiles of 64 x tile_rows nodes with the order field recomputed on a
  *    halo: 0 one workgroup per tile in table order, 1 tiles grouped per XCD,
  *    2 persistent workgroups (persist_blocks_per_cu x 256 CUs) striding the table.
  *  tile_rows: rows per tile for schedules 0..2 (1, 2, 4 or 8).
- *  chunk_rows: target rows per strip chunk for schedules 3..5 (0, or 4..4096;
+ *  chunk_rows: target rows per strip chunk for schedules 3..6 (0, or 4..4096;
  *    default 8): each strip column is cut into chunks of about that height that
  *    start an even number of rows apart, so that the results do not depend on it.
  *    From 12 rows on, the last rows of the last columns of each XCD's run go to
  *    short chunks (a quarter of the height, at least 4 rows) that end the step.
  *  graph_steps: time steps captured per HIP graph (even, >= 2; 0 = no graphs).
- *  fp64_arith: 1 evaluates the collision in FP64 (schedules 3..5; schedules 0..2
+ *  fp64_arith: 1 evaluates the collision in FP64 (schedules 3..6; schedules 0..2
  *    then compute the whole step in FP64), 0 in FP32.  The stored state is FP32
  *    either way (same memory traffic). */
 typedef struct {

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbcap.so")
 
 SOURCES = ["lb_api.hip", "lb_thermo.cpp", "lb_analysis.cpp", "mlp.hip"]
-HEADERS = ["lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_strip_table.h", "lb_wide.h", "lb_wide2.h", "lb_thermo.h"]
+HEADERS = ["lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_strip_table.h", "lb_wide.h", "lb_wide2.h", "lb_wmom.h", "lb_thermo.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -28,6 +28,7 @@
 #include "lb_strip_table.h"
 #include "lb_wide.h"
 #include "lb_wide2.h"
+#include "lb_wmom.h"
 #include "lb_thermo.h"
 
 using namespace lbk;
@@ -343,6 +344,7 @@ struct lb_ctx {
     long timed_steps = 0;
     int unstable = 0;
     bool any_force = false;   // some capillary has a body force (row sweeps keep the forcing terms)
+    int mstore = 0;           // 1: the arenas hold the seven-plane post-collision state (schedule 6)
 };
 
 namespace {
@@ -354,6 +356,37 @@ void drop_graphs(lb_ctx* c) {
         c->gexec[p] = nullptr;
         c->graph[p] = nullptr;
     }
+}
+
+// Converts the f regions of arena b of every capillary to the storage
+// `to_state` (1: seven-plane post-collision state, 0: nine populations).
+lb_status convert_arena(lb_ctx* c, int b, int to_state) {
+    long long most = 0;
+    for (const CapDev& d : c->L.caps) most = std::max(most, d.plane);
+    const int gx = (int)std::min<long long>((most + 255) / 256, 1024);
+    if (to_state)
+        hipLaunchKernelGGL(lb_convert_kernel<true>, dim3(gx, c->n), dim3(256), 0, c->stream, c->d_caps, c->arena[b]);
+    else
+        hipLaunchKernelGGL(lb_convert_kernel<false>, dim3(gx, c->n), dim3(256), 0, c->stream, c->d_caps, c->arena[b]);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+// Records the storage the arenas hold (without converting them).
+lb_status mark_storage(lb_ctx* c, int m) {
+    c->mstore = m;
+    for (CapDev& d : c->L.caps) d.mstore = m;
+    HIP_TRY(hipMemcpyAsync(c->d_caps, c->L.caps.data(), sizeof(CapDev) * c->n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+// Switches both arenas (all capillaries, retired ones too) to storage m.
+lb_status set_storage(lb_ctx* c, int m) {
+    if (m == c->mstore) return LB_OK;
+    for (int b = 0; b < 2; ++b)
+        if (lb_status s = convert_arena(c, b, m)) return s;
+    return mark_storage(c, m);
 }
 
 // output columns per strip of the row-sweep schedules (3: one wavefront, 4: a workgroup)
@@ -428,7 +461,9 @@ void launch_strip_f(lb_ctx* c, const StripArgs& a, int grid, bool fused) {
         else
             hipLaunchKernelGGL((lb_strip_vdw<CT, FORCE>), dim3(grid), dim3(SW), 0, c->stream, a);
     } else {
-        if (wide)
+        if (c->cfg.schedule == 6)
+            hipLaunchKernelGGL((lb_wmom_bin<MT, CT, ST, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
+        else if (wide)
             hipLaunchKernelGGL((lb_wide_bin<MT, CT, ST, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
         else
             hipLaunchKernelGGL((lb_strip_bin<MT, CT, ST, FORCE>), dim3(grid), dim3(SW), STRIP_BIN_LDS_PAD,
@@ -505,27 +540,53 @@ void enqueue_step(lb_ctx* c, bool init, bool fused = false) {
 }
 
 // Every launch reads arena cur and writes the other one, so each flips cur,
-// whether it advances one time step or two.
+// whether it advances one time step or two.  A run of graph_steps steps is
+// one graph per starting arena (capture does not execute).
+lb_status capture_graph(lb_ctx* c, int p) {
+    const int spl = steps_per_launch(c->cfg);
+    const int launches = c->cfg.graph_steps / spl;
+    const int keep = c->cur;
+    c->cur = p;
+    HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    for (int s = 0; s < launches; ++s) {
+        enqueue_step(c, false, spl == 2);
+        c->cur ^= 1;
+    }
+    c->cur = keep;
+    hipGraph_t gr = nullptr;
+    HIP_TRY(hipStreamEndCapture(c->stream, &gr));
+    c->graph[p] = gr;
+    HIP_TRY(hipGraphInstantiate(&c->gexec[p], gr, nullptr, nullptr, 0));
+    return LB_OK;
+}
+
+bool graphs_used(const lb_ctx* c, long n) {
+    const int K = c->cfg.graph_steps;
+    return K >= 2 && (K % 2) == 0 && n >= K && c->ntiles > 0;
+}
+
+// The graphs a run of n steps will replay, captured beforehand (so that the
+// capture is not inside a caller's timed region).
+lb_status prepare_graphs(lb_ctx* c, long n) {
+    if (!graphs_used(c, n)) return LB_OK;
+    const int launches = c->cfg.graph_steps / steps_per_launch(c->cfg);
+    const int parities = (launches & 1) && n >= 2L * c->cfg.graph_steps ? 2 : 1;
+    for (int q = 0; q < parities; ++q) {
+        const int p = c->cur ^ q;
+        if (!c->gexec[p])
+            if (lb_status s = capture_graph(c, p)) return s;
+    }
+    return LB_OK;
+}
+
 lb_status run_steps(lb_ctx* c, long n) {
     const int K = c->cfg.graph_steps;
     const int spl = steps_per_launch(c->cfg);
-    if (K >= 2 && (K % 2) == 0 && n >= K && c->ntiles > 0) {
+    if (graphs_used(c, n)) {
         const int launches = K / spl;   // K is even
         while (n >= K) {
-            if (!c->gexec[c->cur]) {
-                // a graph per starting arena; capture does not execute
-                const int p = c->cur;
-                HIP_TRY(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-                for (int s = 0; s < launches; ++s) {
-                    enqueue_step(c, false, spl == 2);
-                    c->cur ^= 1;
-                }
-                c->cur = p;
-                hipGraph_t gr = nullptr;
-                HIP_TRY(hipStreamEndCapture(c->stream, &gr));
-                c->graph[p] = gr;
-                HIP_TRY(hipGraphInstantiate(&c->gexec[p], gr, nullptr, nullptr, 0));
-            }
+            if (!c->gexec[c->cur])
+                if (lb_status s = capture_graph(c, c->cur)) return s;
             HIP_TRY(hipGraphLaunch(c->gexec[c->cur], c->stream));
             c->cur ^= launches & 1;
             c->t += K;
@@ -815,6 +876,8 @@ lb_status lb_step(lb_ctx* c, long nsteps) { return lb_batch_step(c, nsteps, 0); 
 lb_status lb_batch_step(lb_ctx* c, long nsteps, int sample_every) {
     if (lb_status s = check_ctx(c)) return s;
     if (nsteps < 0 || sample_every < 0) return fail(LB_EINVAL, "negative step count");
+    // graphs are captured before the timing events, which then bracket the launches only
+    if (lb_status s = prepare_graphs(c, sample_every > 0 ? std::min<long>(nsteps, sample_every) : nsteps)) return s;
     HIP_TRY(hipEventRecord(c->ev0, c->stream));
     long left = nsteps;
     while (left > 0) {
@@ -990,7 +1053,10 @@ struct CkptHeader {
     int64_t t;
     int32_t n, model;
     int64_t floats;
+    int32_t mstore, pad;   // storage of the saved f planes
 };
+
+constexpr uint64_t CKPT_MAGIC = 0x4C42434150434B33ULL;
 
 static uint64_t setup_hash(const lb_ctx* c) {
     uint64_t h = fnv1a(c->P.data(), sizeof(lb_params) * c->P.size());
@@ -1015,7 +1081,7 @@ size_t lb_checkpoint_bytes(const lb_ctx* c) {
 lb_status lb_save(lb_ctx* c, void* host_buf, size_t bytes) {
     if (lb_status s = check_ctx(c)) return s;
     if (!host_buf || bytes < lb_checkpoint_bytes(c)) return fail(LB_EINVAL, "checkpoint buffer too small");
-    CkptHeader h{0x4C42434150434B32ULL, setup_hash(c), c->t, c->n, c->model, c->L.arena_floats};
+    CkptHeader h{CKPT_MAGIC, setup_hash(c), c->t, c->n, c->model, c->L.arena_floats, c->mstore, 0};
     char* p = (char*)host_buf;
     std::memcpy(p, &h, sizeof h);
     std::memcpy(p + sizeof h, c->active.data(), sizeof(int) * c->n);
@@ -1041,7 +1107,8 @@ lb_status lb_load(lb_ctx* c, const void* host_buf, size_t bytes) {
     if (!host_buf || bytes < lb_checkpoint_bytes(c)) return fail(LB_EINVAL, "checkpoint buffer too small");
     CkptHeader h;
     std::memcpy(&h, host_buf, sizeof h);
-    if (h.magic != 0x4C42434150434B32ULL || h.hash != setup_hash(c) || h.n != c->n || h.floats != c->L.arena_floats)
+    if (h.magic != CKPT_MAGIC || h.hash != setup_hash(c) || h.n != c->n || h.floats != c->L.arena_floats ||
+        (h.mstore != 0 && h.mstore != 1))
         return fail(LB_EINVAL, "checkpoint belongs to another setup");
     const char* p = (const char*)host_buf;
     std::vector<int> act(c->n);
@@ -1064,6 +1131,9 @@ lb_status lb_load(lb_ctx* c, const void* host_buf, size_t bytes) {
         d.par = 0;
         d.active = c->active[k];
     }
+    // an image of the other storage is converted to the context's
+    if (h.mstore != c->mstore)
+        if (lb_status s = convert_arena(c, c->cur, c->mstore)) return s;
     HIP_TRY(hipStreamSynchronize(c->stream));
     HIP_TRY(hipMemcpyAsync(c->d_caps, c->L.caps.data(), sizeof(CapDev) * c->n, hipMemcpyHostToDevice, c->stream));
     c->t = (long)h.t;
@@ -1081,9 +1151,11 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
     if (!c || !cfg) return fail(LB_EINVAL, "null argument");
     const int r = cfg->tile_rows;
     if (r != 1 && r != 2 && r != 4 && r != 8) return fail(LB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
-    if (cfg->schedule < 0 || cfg->schedule > 5) return fail(LB_EINVAL, "schedule must be 0, 1, 2, 3, 4 or 5");
+    if (cfg->schedule < 0 || cfg->schedule > 6) return fail(LB_EINVAL, "schedule must be 0, 1, 2, 3, 4, 5 or 6");
     if (cfg->schedule == 5 && c->model != LB_VDW)
         return fail(LB_EINVAL, "schedule 5 (two steps per sweep) is built for the van der Waals model only");
+    if (cfg->schedule == 6 && c->model != LB_BINARY)
+        return fail(LB_EINVAL, "schedule 6 (moment storage) is built for the binary model only");
     if (cfg->schedule == 2 && (cfg->persist_blocks_per_cu < 1 || cfg->persist_blocks_per_cu > 32))
         return fail(LB_EINVAL, "persistent workgroups per CU must be in 1..32");
     if (cfg->graph_steps != 0 && (cfg->graph_steps < 2 || cfg->graph_steps % 2 != 0 || cfg->graph_steps > 4096))
@@ -1096,6 +1168,7 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
                         strip_width(*cfg) != strip_width(c->cfg);
     c->cfg = *cfg;
     drop_graphs(c);
+    if (lb_status s = set_storage(c, cfg->schedule == 6 ? 1 : 0)) return s;
     if (retile) return upload_tiles(c);
     return LB_OK;
 }
@@ -1135,6 +1208,7 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     HIP_TRY(hipMemcpyAsync((char*)backup.p + ab, c->arena[1], ab, hipMemcpyDeviceToDevice, c->stream));
     const long t0 = c->t;
     const int cur0 = c->cur;
+    const int mstore0 = c->mstore;
     const lb_launch_config orig = c->cfg;
     std::vector<lb_launch_config> cand;
     const int ar = orig.fp64_arith;   // the arithmetic is a choice of the caller, not tuned
@@ -1142,6 +1216,8 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     for (int ch : {8, 12, 16, 32}) cand.push_back({orig.tile_rows, 4, 4, 0, ar, ch});
     if (c->model == LB_VDW)
         for (int ch : {8, 12, 16, 24, 32}) cand.push_back({orig.tile_rows, 5, 4, 0, ar, ch});
+    else
+        for (int ch : {8, 12, 16, 32}) cand.push_back({orig.tile_rows, 6, 4, 0, ar, ch});
     for (int r : {4, 8}) {
         cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
         cand.push_back({r, 2, 4, 0, ar, orig.chunk_rows});
@@ -1179,6 +1255,8 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->cur = cur0;
     c->t = t0;
+    // the backup holds the storage of the start; the final setting converts it if needed
+    if (lb_status s2 = mark_storage(c, mstore0)) return s2;
     if (st) {
         const std::string msg = g_err;
         lb_set_launch_config(c, &orig);

@@ -217,8 +217,40 @@ __device__ __forceinline__ void vdw_lambdas(R inv_omega_mh, R dp0, R& lam, R& la
     lam_b = R(0.5) * base;
 }
 
+// The post-collision state of a node.  With the rates of Appendix A the
+// moments e, eps, qx and qy relax fully to their equilibria (qx* = -jx*,
+// qy* = -jy*), so f* = M^-1 m* depends on seven numbers only: the density
+// (minus rho_ref), the momentum j* (with the forcing), the common parts b and d
+// of the axis and diagonal populations (e* and eps*, minus their reference
+// values X_ref/3 and X_ref/12) and the relaxed stresses pxx*, pxy*.
+template <typename R>
+struct PostState {
+    R drho, jx, jy, b, d, pxx, pxy;
+};
+
+// The shifted post-collision populations f* = M^-1 m* of a post-collision
+// state.  The even (common) part of each opposite pair is formed first and the
+// small momentum term added last, so both members of a pair round at the same
+// magnitude and their difference keeps the momentum.
+template <typename R>
+__device__ __forceinline__ void pops_of_state(const PostState<R>& s, R (&o)[9]) {
+    const R a7 = R(0.25) * s.pxx, a8 = R(0.25) * s.pxy;
+    const R jx3 = s.jx * (R(1) / R(3)), jy3 = s.jy * (R(1) / R(3));
+    const R jpp = (s.jx + s.jy) * (R(1) / R(12)), jpm = (s.jx - s.jy) * (R(1) / R(12));
+    const R cx = s.b + a7, cy = s.b - a7, cp = s.d + a8, cm = s.d - a8;
+    o[1] = cx + jx3;
+    o[2] = cx - jx3;
+    o[3] = cy + jy3;
+    o[4] = cy - jy3;
+    o[5] = cp + jpp;
+    o[6] = cp - jpp;
+    o[7] = cm - jpm;
+    o[8] = cm + jpm;
+    o[0] = s.drho - R(4) * (s.b + s.d);   // rest population minus rho_ref - 5/3 X_ref
+}
+
 // MRT collision of one node in moment space (Appendix A rates, Guo source
-// (I - S/2) M F), returning the shifted post-collision populations.
+// (I - S/2) M F), returning the post-collision state.
 //   m:   pre-collision moments (rho - rho_ref, j after rest, pxx, pxy)
 //   dX:  X - X_ref, X = p0 - kappa q lap(q) the isotropic part of Eq. (equilibrium)
 //   lam, lam_b: coefficients of the traceless part and of the isotropic part of
@@ -229,8 +261,8 @@ __device__ __forceinline__ void vdw_lambdas(R inv_omega_mh, R dp0, R& lam, R& la
 // in the binary model) and FORCE = false the forcing terms (F must then be 0);
 // the results are the same, with fewer instructions.
 template <typename R, typename S = R, bool LAM = true, bool FORCE = true>
-__device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX, R lam, R lam_b,
-                                        R omega, R dxq, R dyq, R F, R (&o)[9]) {
+__device__ __forceinline__ PostState<R> collide_state(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX,
+                                                      R lam, R lam_b, R omega, R dxq, R dyq, R F) {
     const R kappa = (R)c.kappa;
     const R u2 = rho * (ux * ux + uy * uy);
     const R trQ = LAM ? u2 + R(4) * lam_b * (ux * dxq + uy * dyq) : u2;
@@ -255,22 +287,14 @@ __device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho,
     const R pxs = FORCE ? pxr + hw * R(2) * uF : pxr;
     const R pys = FORCE ? pyr + hw * (uy * F) : pyr;
     const R jxs = FORCE ? m.jx + F : m.jx, jys = m.jy;   // qx*, qy* = -jx*, -jy*
-    const R a7 = R(0.25) * pxs, a8 = R(0.25) * pys;
-    const R jx3 = jxs * (R(1) / R(3)), jy3 = jys * (R(1) / R(3));
-    const R jpp = (jxs + jys) * (R(1) / R(12)), jpm = (jxs - jys) * (R(1) / R(12));
-    // the even (common) part of each opposite pair is formed first and the
-    // small momentum term added last, so both members of a pair round at the
-    // same magnitude and their difference keeps the momentum
-    const R cx = b + a7, cy = b - a7, cp = d + a8, cm = d - a8;
-    o[1] = cx + jx3;
-    o[2] = cx - jx3;
-    o[3] = cy + jy3;
-    o[4] = cy - jy3;
-    o[5] = cp + jpp;
-    o[6] = cp - jpp;
-    o[7] = cm - jpm;
-    o[8] = cm + jpm;
-    o[0] = m.drho - R(4) * (b + d);   // rest population minus rho_ref - 5/3 X_ref
+    return PostState<R>{m.drho, jxs, jys, b, d, pxs, pys};
+}
+
+// The collision returning the shifted post-collision populations.
+template <typename R, typename S = R, bool LAM = true, bool FORCE = true>
+__device__ __forceinline__ void collide(const CapDev& c, const Mom<R>& m, R rho, R ux, R uy, R dX, R lam, R lam_b,
+                                        R omega, R dxq, R dyq, R F, R (&o)[9]) {
+    pops_of_state(collide_state<R, S, LAM, FORCE>(c, m, rho, ux, uy, dX, lam, lam_b, omega, dxq, dyq, F), o);
 }
 
 // g^eq_i (i >= 1) of Appendix A from phi, u and Gamma mu.
@@ -599,12 +623,19 @@ __global__ void lb_moments_kernel(const CapDev* caps, int cap, const float* __re
         if (!g.solid(x, y)) {
             const Hood h = hood_of(g, x, y);
             const long long own = (long long)y * g.pitch + x;
-            float f[9];
+            float jx, jy;
+            if (c.mstore) {   // planes drho, jx*, jy*, ...
+                r = c.rho_ref + st[c.off_f + own];
+                jx = st[c.off_f + c.plane + own];
+                jy = st[c.off_f + 2 * c.plane + own];
+            } else {
+                float f[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) f[i] = st[c.off_f + i * c.plane + own];
-            r = c.rho_ref + sum9(f);
-            const float jx = ((f[1] - f[2]) + (f[5] - f[6])) + (f[8] - f[7]);
-            const float jy = ((f[3] - f[4]) + (f[5] - f[6])) + (f[7] - f[8]);
+                for (int i = 0; i < 9; ++i) f[i] = st[c.off_f + i * c.plane + own];
+                r = c.rho_ref + sum9(f);
+                jx = ((f[1] - f[2]) + (f[5] - f[6])) + (f[8] - f[7]);
+                jy = ((f[3] - f[4]) + (f[5] - f[6])) + (f[7] - f[8]);
+            }
             const float F = h.solid ? 0.f : c.Fx;
             u = (jx - 0.5f * F) / r;
             v = jy / r;
@@ -623,6 +654,9 @@ __device__ __forceinline__ float centre_q(const CapDev& c, const float* __restri
                                           const float* __restrict__ prev, int x, int ya, int yb) {
     if (MODEL == 1)
         return 0.5f * (prev[c.off_phi + (long long)ya * c.pitch + x] + prev[c.off_phi + (long long)yb * c.pitch + x]);
+    if (c.mstore)
+        return 0.5f * ((c.rho_ref + st[c.off_f + (long long)ya * c.pitch + x]) +
+                       (c.rho_ref + st[c.off_f + (long long)yb * c.pitch + x]));
     float fa[9], fb[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -698,11 +732,17 @@ __global__ void lb_health_kernel(const CapDev* caps, const TileDev* tiles, int n
             const long long own = (long long)y * g.pitch + x;
             float s = c.rho_ref;
             bool bad = false;
+            if (c.mstore) {   // the state's planes; the first one is drho
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const float v = st[c.off_f + i * c.plane + own];
-                bad |= !isfinite(v);
-                s += v;
+                for (int i = 0; i < 7; ++i) bad |= !isfinite(st[c.off_f + i * c.plane + own]);
+                s += st[c.off_f + own];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const float v = st[c.off_f + i * c.plane + own];
+                    bad |= !isfinite(v);
+                    s += v;
+                }
             }
             if (MODEL == 1) bad |= !isfinite(st[c.off_phi + own]);
             if (bad || !(s > 0.f)) atomicOr(&flags[t.cap], 1);

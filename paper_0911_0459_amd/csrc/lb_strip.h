@@ -505,6 +505,38 @@ __device__ __forceinline__ void vdw_node_collide(const CapDev& c, const Mom<floa
     collide<CT, float, true, FORCE>(cd, m, rho, ux, uy, dX, lam, lam_b, omega, (CT)dxf, (CT)dyf, F, o);
 }
 
+// Post-collision state of one fluid node of the binary model (the wide row
+// sweeps share it): from the FP32 moments of its pulled populations, its
+// order parameter and the stencils of phi, the bulk pressure and interface
+// terms of X (Sec. 3.1), the phi-dependent relaxation rate of Eq. (nu) and the
+// MRT relaxation with the non-shear part in type CT, the shear part in ST.
+template <typename CT, typename ST, bool FORCE>
+__device__ __forceinline__ PostState<CT> bin_node_state(const CapDev& c, const Mom<float>& mom, unsigned sm,
+                                                        float phi, float dxf, float dyf, float lapf) {
+    // constants of the FP64 part, converted where used (see uniform_opaque)
+    CapDev cd = c;
+    uniform_opaque(cd.kappa);
+    uniform_opaque(cd.Fx);
+    uniform_opaque(cd.rho_ref);
+    uniform_opaque(cd.phib);
+    uniform_opaque(cd.B);
+    const Mom<CT> mc{(CT)mom.drho, (CT)mom.jx, (CT)mom.jy, (CT)mom.pxx, (CT)mom.pxy};
+    const CT F = (FORCE && !sm) ? (CT)cd.Fx : CT(0);
+    const CT rho = (CT)cd.rho_ref + mc.drho;
+    const CT inv_rho = recip(rho);
+    const CT ux = (FORCE ? mc.jx + CT(0.5) * F : mc.jx) * inv_rho, uy = mc.jy * inv_rho;
+    const CT ph = (CT)phi, phib = (CT)cd.phib;
+    const CT dX = mc.drho * (CT(1) / CT(3)) +
+                  CT(0.25) * (CT)cd.B * ((ph - phib) * (ph + phib)) * (CT(3) * ph * ph + phib * phib) -
+                  (CT)cd.kappa * ph * (CT)lapf;
+    // the relaxation rate only scales the shear stresses (FP32) and the
+    // forcing term: FP32 with the hardware reciprocal (1 ulp)
+    const float pc = phi < -1.f ? -1.f : (phi > 1.f ? 1.f : phi);
+    const float nu = cd.nu_g + 0.5f * (pc + 1.f) * (cd.nu_l - cd.nu_g);
+    const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
+    return collide_state<CT, ST, false, FORCE>(cd, mc, rho, ux, uy, dX, CT(0), CT(0), omega, (CT)dxf, (CT)dyf, F);
+}
+
 template <typename CT, bool FORCE = true>
 __global__ void __launch_bounds__(SW) lb_strip_vdw(StripArgs a) {
     const int si = strip_index(a);

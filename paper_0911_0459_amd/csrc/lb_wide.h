@@ -221,30 +221,10 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
         // (d) collision and phi update of row y (main lanes)
         if (out_col && fl_cur) {
             // constants of the FP64 part, converted where used (see uniform_opaque)
-            CapDev cd = c;
-            uniform_opaque(cd.kappa);
-            uniform_opaque(cd.Fx);
-            uniform_opaque(cd.rho_ref);
-            uniform_opaque(cd.phib);
-            uniform_opaque(cd.B);
             const int s0 = sl(0);
             const float phi = RG[s0][R_PH][pj];
-            const Mom<CT> mc{(CT)mom_cur.drho, (CT)mom_cur.jx, (CT)mom_cur.jy, (CT)mom_cur.pxx, (CT)mom_cur.pxy};
-            const CT F_cur = (FORCE && !sm_cur) ? (CT)cd.Fx : CT(0);
-            const CT rho_c = (CT)cd.rho_ref + mc.drho;
-            const CT inv_rho = recip(rho_c);
-            const CT ux_cur = (FORCE ? mc.jx + CT(0.5) * F_cur : mc.jx) * inv_rho, uy_cur = mc.jy * inv_rho;
-            const CT ph = (CT)phi, phib = (CT)cd.phib;
-            const CT dX = mc.drho * (CT(1) / CT(3)) +
-                          CT(0.25) * (CT)cd.B * ((ph - phib) * (ph + phib)) * (CT(3) * ph * ph + phib * phib) -
-                          (CT)cd.kappa * ph * (CT)lap_cur;
-            // the relaxation rate only scales the shear stresses (FP32) and the
-            // forcing term: FP32 with the hardware reciprocal (1 ulp)
-            const float pc = phi < -1.f ? -1.f : (phi > 1.f ? 1.f : phi);
-            const float nu = cd.nu_g + 0.5f * (pc + 1.f) * (cd.nu_l - cd.nu_g);
-            const CT omega = (CT)(2.f * __builtin_amdgcn_rcpf(6.f * nu + 1.f));
             CT o[9];
-            collide<CT, ST, false, FORCE>(cd, mc, rho_c, ux_cur, uy_cur, dX, CT(0), CT(0), omega, (CT)dx_cur, (CT)dy_cur, F_cur, o);
+            pops_of_state(bin_node_state<CT, ST, FORCE>(c, mom_cur, sm_cur, phi, dx_cur, dy_cur, lap_cur), o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);

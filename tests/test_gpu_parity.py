@@ -68,30 +68,33 @@ def test_vdw_capillary_256x64_1e4_steps(L):
 def test_binary_capillary_1e4_steps(L):
     """Binary capillary (ratio 10, 60 degrees) on a 256x64 lattice."""
     w = small_binary()
-    gpu, lg = gpu_run(L, w, 10_000, sample_every=500)
     orc, lo = run_oracle(w, 10_000, sample_every=500)
-    drho, dphi, du = field_errors(w, gpu, orc)
-    print(f"binary 1e4: max rel drho {drho:.3e}, max dphi {dphi:.3e}, du {du:.3e}, "
-          f"max dl {np.abs(lg - lo).max():.3e}")
-    assert drho <= 1e-4 and dphi <= 1e-4
-    assert np.abs(lg - lo).max() <= 0.5
+    for cfg in (None, dict(schedule=6, chunk_rows=12)):   # population and moment storage
+        gpu, lg = gpu_run(L, w, 10_000, sample_every=500, cfg=cfg)
+        drho, dphi, du = field_errors(w, gpu, orc)
+        print(f"binary 1e4 {cfg}: max rel drho {drho:.3e}, max dphi {dphi:.3e}, du {du:.3e}, "
+              f"max dl {np.abs(lg - lo).max():.3e}")
+        assert drho <= 1e-4 and dphi <= 1e-4
+        assert np.abs(lg - lo).max() <= 0.5
 
 
 def test_binary_capillary_1024x128_1e4_steps(L):
     """The binary capillary at its real size: 1024x128, tube H=40 and length
-    768, ratio 10, 60 degrees, seed 2, default launch shape, 10^4 steps against
-    the oracle, the filled length compared every 500 steps."""
+    768, ratio 10, 60 degrees, seed 2, 10^4 steps against the oracle in the
+    default launch shape and in the moment storage (schedule 6), the filled
+    length compared every 500 steps."""
     w = I.binary_capillary_1024x128()
-    print(f"binary 1024x128 1e4: GPU run", flush=True)
-    gpu, lg = gpu_run(L, w, 10_000, sample_every=500)
     print(f"binary 1024x128 1e4: oracle run", flush=True)
     orc, lo = run_oracle(w, 10_000, sample_every=500)
-    drho, dphi, du = field_errors(w, gpu, orc)
-    print(f"binary 1024x128 1e4: max rel drho {drho:.3e}, max dphi {dphi:.3e}, du {du:.3e}, "
-          f"max dl {np.abs(lg - lo).max():.3e}, l_oracle {lo[0]:.2f} -> {lo[-1]:.2f}")
-    assert drho <= 1e-4 and dphi <= 1e-4
-    assert np.abs(lg - lo).max() <= 0.5
     assert lo[-1] > lo[0] + 5.0          # the liquid is filling the tube
+    for cfg in (None, dict(schedule=6, chunk_rows=12)):   # population and moment storage
+        print(f"binary 1024x128 1e4: GPU run {cfg}", flush=True)
+        gpu, lg = gpu_run(L, w, 10_000, sample_every=500, cfg=cfg)
+        drho, dphi, du = field_errors(w, gpu, orc)
+        print(f"binary 1024x128 1e4 {cfg}: max rel drho {drho:.3e}, max dphi {dphi:.3e}, du {du:.3e}, "
+              f"max dl {np.abs(lg - lo).max():.3e}, l_oracle {lo[0]:.2f} -> {lo[-1]:.2f}")
+        assert drho <= 1e-4 and dphi <= 1e-4
+        assert np.abs(lg - lo).max() <= 0.5
 
 
 # ---- tight short-run parity across tiles, tails and launch shapes --------------
@@ -409,7 +412,7 @@ def test_autotune_keeps_state(L):
     cfg0 = a.launch_config()
     a.step(40)
     cfg, us = a.autotune(trial_steps=6)
-    assert cfg.schedule in (0, 1, 2, 3, 4) and us > 0
+    assert cfg.schedule in (0, 1, 2, 3, 4, 6) and us > 0
     assert a.t == 40
     a.step(60)
     # a new lattice starts from the default shape, and takes the tuned one only
@@ -458,7 +461,7 @@ def test_every_strip_chunking_fits_one_capillary(L):
     w = I.sweep_capillary(4, 144)
     assert w.geom.tube_h == 11
     lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), w.initial_field())
-    for schedule in (3, 4):
+    for schedule in (3, 4, 6):
         for ch in (0, 4, 6, 8, 12, 16, 32):
             lat.set_launch_config(schedule=schedule, chunk_rows=ch, fp64_arith=1)
         lat.set_launch_config(schedule=4, chunk_rows=12, fp64_arith=1)
