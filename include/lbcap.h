@@ -284,14 +284,14 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    ends with one launch of schedule 4.  The same arithmetic per step.
  *    6 (binary model only) the strips of 4 over a stored state of seven FP32
  *    planes instead of nine populations: with the rates of Appendix A the
- *    post-collision populations of a node follow from rho - rho_ref, j*, the
+ *    post-collision populations of a node follow from rho - rho_ref, j* / 3, the
  *    common parts of the axis and of the diagonal populations, pxx* and pxy*,
  *    so a step moves 32 instead of 40 bytes per node (phi included).  The
  *    sweep rebuilds the populations of each row once, into LDS, and pulls
  *    from there.  Setting this schedule converts the stored state in place
  *    (both buffers); leaving it converts back.  Results agree with schedule 4
- *    to rounding (the populations are rounded to FP32 after the rebuild
- *    instead of before the store).
+ *    to rounding (the populations are rebuilt in FP32 from the stored FP32
+ *    state instead of being rounded once from the collision's arithmetic).
  *    0..2 tiles of 64 x tile_rows nodes with the order field recomputed on a
  *    halo: 0 one workgroup per tile in table order, 1 tiles grouped per XCD,
  *    2 persistent workgroups (persist_blocks_per_cu x 256 CUs) striding the table.

@@ -1217,7 +1217,7 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     if (c->model == LB_VDW)
         for (int ch : {8, 12, 16, 24, 32}) cand.push_back({orig.tile_rows, 5, 4, 0, ar, ch});
     else
-        for (int ch : {8, 12, 16, 32}) cand.push_back({orig.tile_rows, 6, 4, 0, ar, ch});
+        for (int ch : {12, 16, 24, 32}) cand.push_back({orig.tile_rows, 6, 4, 0, ar, ch});
     for (int r : {4, 8}) {
         cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
         cand.push_back({r, 2, 4, 0, ar, orig.chunk_rows});

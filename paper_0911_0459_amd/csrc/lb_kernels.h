@@ -624,10 +624,10 @@ __global__ void lb_moments_kernel(const CapDev* caps, int cap, const float* __re
             const Hood h = hood_of(g, x, y);
             const long long own = (long long)y * g.pitch + x;
             float jx, jy;
-            if (c.mstore) {   // planes drho, jx*, jy*, ...
+            if (c.mstore) {   // planes drho, jx*/3, jy*/3, ...
                 r = c.rho_ref + st[c.off_f + own];
-                jx = st[c.off_f + c.plane + own];
-                jy = st[c.off_f + 2 * c.plane + own];
+                jx = 3.f * st[c.off_f + c.plane + own];
+                jy = 3.f * st[c.off_f + 2 * c.plane + own];
             } else {
                 float f[9];
 #pragma unroll
