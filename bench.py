@@ -31,6 +31,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_LUP = {"vdw": 72, "binary": 80}   # read + write of every stored FP32 value (9 f; binary + phi)
+BYTES_PER_LUP_MOMENT_STORAGE = 64            # schedule 6 (binary): 7 state planes + phi, read and written
+
+
+def bytes_per_lup(model: str, schedule: int) -> int:
+    """Algorithmic HBM bytes per fluid-node update: every stored FP32 value
+    read and written once, in the storage the launch shape uses."""
+    return BYTES_PER_LUP_MOMENT_STORAGE if (model == "binary" and schedule == 6) else BYTES_PER_LUP[model]
 
 
 # the step kernels and the strip table that shapes their traffic
@@ -325,7 +332,7 @@ def main():
 
     fluid = lat.fluid_nodes
     mlups = fluid * args.steps / elapsed / 1e6
-    bpl = BYTES_PER_LUP[model]
+    bpl = bytes_per_lup(model, cfg.schedule)
     achieved = bpl * fluid / (us_kernel * 1e-6) / 1e9 if us_kernel > 0 else None
     kname = ({3: "lb_strip_", 4: "lb_wide_", 5: "lb_wide2_", 6: "lb_wmom_"}[cfg.schedule] + ("bin" if model == "binary" else "vdw")
              if cfg.schedule in (3, 4, 5, 6) else f"lb_step_kernel_{model}_{cfg.tile_rows}")
