@@ -564,6 +564,8 @@ FUSED_GEOMS = {
     "wide700x45": I.Geometry(nx=700, ny=45, x_in=250, tube_len=450, tube_h=17, y0=14),
     "ends520x41": I.Geometry(nx=520, ny=41, x_in=150, tube_len=280, tube_h=15, y0=13),
     "periodic5x3": I.Geometry(nx=5, ny=3),
+    # one-row walls: the tube's wall rows are neighbours through the periodic y boundary
+    "thinwall300x22": I.Geometry(nx=300, ny=22, x_in=100, tube_len=200, tube_h=20, y0=1),
 }
 
 
