@@ -30,13 +30,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_LUP = {"vdw": 72, "binary": 80}   # read + write of every stored FP32 value (9 f; binary + phi)
+# Algorithmic bytes per fluid-node update of the method: every FP32 population
+# (and, binary, phi) read and written once.  The roofline's `achieved` uses these.
+BYTES_PER_LUP = {"vdw": 72, "binary": 80}
 BYTES_PER_LUP_MOMENT_STORAGE = 64            # schedule 6 (binary): 7 state planes + phi, read and written
 
 
-def bytes_per_lup(model: str, schedule: int) -> int:
-    """Algorithmic HBM bytes per fluid-node update: every stored FP32 value
-    read and written once, in the storage the launch shape uses."""
+def stored_bytes_per_lup(model: str, schedule: int) -> int:
+    """Bytes per fluid-node update that the launch shape's own storage must
+    move: the method's figure, or 64 B for the binary moment storage, which
+    stores the seven numbers that fix the post-collision populations."""
     return BYTES_PER_LUP_MOMENT_STORAGE if (model == "binary" and schedule == 6) else BYTES_PER_LUP[model]
 
 
@@ -332,12 +335,14 @@ def main():
 
     fluid = lat.fluid_nodes
     mlups = fluid * args.steps / elapsed / 1e6
-    bpl = bytes_per_lup(model, cfg.schedule)
+    bpl = BYTES_PER_LUP[model]
+    sbpl = stored_bytes_per_lup(model, cfg.schedule)
     achieved = bpl * fluid / (us_kernel * 1e-6) / 1e9 if us_kernel > 0 else None
     kname = ({3: "lb_strip_", 4: "lb_wide_", 5: "lb_wide2_", 6: "lb_wmom_"}[cfg.schedule] + ("bin" if model == "binary" else "vdw")
              if cfg.schedule in (3, 4, 5, 6) else f"lb_step_kernel_{model}_{cfg.tile_rows}")
     traffic = traffic_from_profiles(kname, args.workload, cfg.asdict())
-    config.update({"model": model, "fluid_nodes": fluid, "launch": cfg.asdict(), "bytes_per_lup": bpl})
+    config.update({"model": model, "fluid_nodes": fluid, "launch": cfg.asdict(), "bytes_per_lup": bpl,
+                   "stored_bytes_per_lup": sbpl})
     out = {
         "metric": "MLUPS (fluid-node updates/s) and fraction of HBM roofline",
         "value": round(mlups, 1),
@@ -360,6 +365,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "traffic": traffic,
+            "frac_of_stored_bytes": round(sbpl / bpl * achieved / HBM_PEAK_GBS, 4) if achieved else None,
             "kernel_us": round(us_kernel, 3),
             "copy_kernel_gbps": copy_bandwidth(L, 10)["gbps"],
         },

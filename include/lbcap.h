@@ -211,6 +211,18 @@ lb_status lb_washburn_length(double t, double l0, double H, double L, double gam
  * theta in (0, 180); LB_EINVAL outside the partial-wetting range. */
 lb_status lb_wall_gradient_for_angle(const lb_params* p, double theta_deg, double* grad);
 
+/* Change the wall gradient of capillary cap (normal derivative of rho/phi at
+ * the wall, normal into the fluid) for the steps that follow: the equilibrium
+ * gradient scanned slowly in time gives the contact angle as a function of the
+ * gradient (Sec. 2.2, Fig. 2).  grad must be finite (LB_EINVAL otherwise).
+ * The library stores post-collision populations: at time T the collision of
+ * time T has been evaluated, so the new gradient enters from the collision of
+ * time T+1 on (one step after a scheme that stores the streamed state).
+ * Synchronises the context stream; captured graphs stay valid (the kernels
+ * read the gradient from the device descriptor).  The parameter hash of checkpoints
+ * includes the gradient: an image saved at another gradient is refused. */
+lb_status lb_set_wall_gradient(lb_ctx* c, int cap, double grad);
+
 /* Coexisting densities of the van der Waals p0 (equal pressure and chemical
  * potential, the Maxwell construction) for the constants in p. */
 lb_status lb_vdw_coexistence(const lb_params* p, double* rho_l, double* rho_g);

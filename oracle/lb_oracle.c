@@ -601,6 +601,15 @@ int orc_create_flow(const orc_params* p, const orc_geom* g, const double* init_q
 
 long orc_time(const orc_state* s) { return s->t; }
 
+int orc_set_wall_gradient(orc_state* s, double wall_grad) {
+    if (!isfinite(wall_grad)) {
+        set_err("wall gradient must be finite");
+        return ORC_EINVAL;
+    }
+    s->p.wall_grad = wall_grad;
+    return ORC_OK;
+}
+
 /* One time step in the order of Eq. (latbolt) / (latbolt2) followed by the
  * wall treatment of Sec. 2.2:
  *   S1 moments, S2 stencils, S3 thermodynamics, S4 equilibria, S5 collision,

@@ -52,6 +52,9 @@ int  orc_create_flow(const orc_params* p, const orc_geom* g, const double* init_
 void orc_free(orc_state* s);
 int  orc_step(orc_state* s, long nsteps);
 long orc_time(const orc_state* s);
+/* Change the wall gradient (normal derivative of rho/phi at the wall) for the
+ * steps that follow: the equilibrium gradient scanned in time, Sec. 2.2, Fig. 2. */
+int  orc_set_wall_gradient(orc_state* s, double wall_grad);
 
 /* Macroscopic fields of the current (post-stream, post-rest) state; solid nodes get 0. */
 void orc_moments(const orc_state* s, double* rho, double* ux, double* uy, double* phi);

@@ -106,6 +106,8 @@ def _load():
     lib.orc_step.restype = C.c_int
     lib.orc_time.argtypes = [C.c_void_p]
     lib.orc_time.restype = C.c_long
+    lib.orc_set_wall_gradient.argtypes = [C.c_void_p, C.c_double]
+    lib.orc_set_wall_gradient.restype = C.c_int
     lib.orc_moments.argtypes = [C.c_void_p, dp, dp, dp, dp]
     lib.orc_get_pop.argtypes = [C.c_void_p, C.c_int, dp]
     lib.orc_interface_length.argtypes = [C.c_void_p, C.c_double, dp, dp]
@@ -219,6 +221,11 @@ class Oracle:
 
     def step(self, n: int):
         _check(_load().orc_step(self._h, int(n)))
+
+    def set_wall_gradient(self, wall_grad: float):
+        """Wall gradient for the following steps (the scan of Sec. 2.2, Fig. 2)."""
+        _check(_load().orc_set_wall_gradient(self._h, float(wall_grad)))
+        self.params.wall_grad = float(wall_grad)
 
     def moments(self):
         n = self.geom.nx * self.geom.ny

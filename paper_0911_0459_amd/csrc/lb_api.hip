@@ -1041,6 +1041,19 @@ lb_status lb_wall_gradient_for_angle(const lb_params* p, double theta_deg, doubl
     return LB_OK;
 }
 
+lb_status lb_set_wall_gradient(lb_ctx* c, int cap, double grad) {
+    if (lb_status s = check_ctx(c)) return s;
+    if (lb_status s = cap_index(c, cap)) return s;
+    if (!std::isfinite(grad)) return fail(LB_EINVAL, "wall gradient must be finite");
+    c->P[cap].wall_grad = grad;
+    c->P[cap].theta_deg = std::nan("");
+    c->L.caps[cap].G = (float)grad;
+    HIP_TRY(hipMemcpyAsync(&c->d_caps[cap], &c->L.caps[cap], sizeof(CapDev), hipMemcpyHostToDevice, c->stream));
+    // the host descriptor may change again before the stream reaches the copy
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
 lb_status lb_vdw_coexistence(const lb_params* p, double* rho_l, double* rho_g) {
     if (!p || !rho_l || !rho_g) return fail(LB_EINVAL, "null argument");
     if (!lbt::vdw_coexistence(p->a, p->b, p->T, rho_l, rho_g)) return fail(LB_EINVAL, "no coexistence (T >= Tc?)");

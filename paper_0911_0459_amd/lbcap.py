@@ -97,6 +97,7 @@ _SIGS = {
                                      _vp]),
     "lb_tube_flow": (C.c_int, [_vp, C.c_int, C.c_int, C.c_double, _dp, _vp]),
     "lb_washburn_length": (C.c_int, [C.c_double] * 8 + [_dp]),
+    "lb_set_wall_gradient": (C.c_int, [_vp, C.c_int, C.c_double]),
     "mlp_init": (C.c_int, [C.POINTER(_vp), C.c_int, _vp]),
     "mlp_free": (None, [_vp]),
     "mlp_param_count": (C.c_long, [_vp]),
@@ -344,6 +345,11 @@ class Lattice:
         line = np.zeros(self.geoms[cap].tube_len)
         _check(_lib.lb_tube_flow(self._h, cap, int(margin), float(v_meniscus), _d(line), C.byref(out)))
         return out, line
+
+    def set_wall_gradient(self, grad: float, cap: int = 0):
+        """Wall gradient of capillary cap for the following steps (the
+        quasistatic scan of Sec. 2.2, Fig. 2)."""
+        _check(_lib.lb_set_wall_gradient(self._h, cap, float(grad)))
 
     def retire(self, cap: int):
         _check(_lib.lb_batch_retire(self._h, cap))
