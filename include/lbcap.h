@@ -314,9 +314,13 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    From 12 rows on, the last rows of the last columns of each XCD's run go to
  *    short chunks (a quarter of the height, at least 4 rows) that end the step.
  *  graph_steps: time steps captured per HIP graph (even, >= 2; 0 = no graphs).
- *  fp64_arith: 1 evaluates the collision in FP64 (schedules 3..6; schedules 0..2
- *    then compute the whole step in FP64), 0 in FP32.  The stored state is FP32
- *    either way (same memory traffic). */
+ *  fp64_arith: 0 (default) evaluates the collision in FP32; 1 evaluates its
+ *    non-shear part in FP64 (schedules 3..6; schedules 0..2 then compute the
+ *    whole step in FP64).  In FP32 the j/3 of the populations is formed with a
+ *    correction of its rounding (the rounded 1/3 would amplify the streamed
+ *    momentum every step); with it both settings hold the 10^4-step oracle
+ *    gates equally.  The stored state is FP32 either way (same memory
+ *    traffic). */
 typedef struct {
     int tile_rows;
     int schedule;

@@ -337,7 +337,7 @@ struct lb_ctx {
     bool own_stream = false;
     int cur = 0;
     long t = 0;
-    lb_launch_config cfg{4, 4, 4, 64, 1, 8};
+    lb_launch_config cfg{4, 4, 4, 64, 0, 8};
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1230,7 +1230,7 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     if (c->model == LB_VDW)
         for (int ch : {8, 12, 16, 24, 32}) cand.push_back({orig.tile_rows, 5, 4, 0, ar, ch});
     else
-        for (int ch : {12, 16, 24, 32}) cand.push_back({orig.tile_rows, 6, 4, 0, ar, ch});
+        for (int ch : {16, 20, 24, 32}) cand.push_back({orig.tile_rows, 6, 4, 0, ar, ch});
     for (int r : {4, 8}) {
         cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
         cand.push_back({r, 2, 4, 0, ar, orig.chunk_rows});

@@ -232,11 +232,29 @@ struct PostState {
 // state.  The even (common) part of each opposite pair is formed first and the
 // small momentum term added last, so both members of a pair round at the same
 // magnitude and their difference keeps the momentum.
+//
+// x/3 in the arithmetic type.  In FP32 the product with 1/3 rounded to FP32
+// (3e-8 too large) would scale every streamed momentum by the same 1 + 3e-8:
+// an amplification of j by that much per step, which moves an interface
+// measurably over 10^4 steps.  There the quotient is corrected with the exact
+// remainder x - 3q (one FMA), which leaves an unbiased rounding error.
+template <typename R>
+__device__ __forceinline__ R third(R x) {
+    if constexpr (sizeof(R) == 4) {
+        const float q = x * (1.f / 3.f);
+        return __builtin_fmaf(__builtin_fmaf(-3.f, q, x), 1.f / 3.f, q);
+    } else {
+        return x * (R(1) / R(3));
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void pops_of_state(const PostState<R>& s, R (&o)[9]) {
     const R a7 = R(0.25) * s.pxx, a8 = R(0.25) * s.pxy;
-    const R jx3 = s.jx * (R(1) / R(3)), jy3 = s.jy * (R(1) / R(3));
-    const R jpp = (s.jx + s.jy) * (R(1) / R(12)), jpm = (s.jx - s.jy) * (R(1) / R(12));
+    const R jx3 = third(s.jx), jy3 = third(s.jy);
+    // j/12 as (j/3)/4 in FP32 (see third); FP64 keeps the direct product
+    const R jpp = sizeof(R) == 4 ? R(0.25) * (jx3 + jy3) : (s.jx + s.jy) * (R(1) / R(12));
+    const R jpm = sizeof(R) == 4 ? R(0.25) * (jx3 - jy3) : (s.jx - s.jy) * (R(1) / R(12));
     const R cx = s.b + a7, cy = s.b - a7, cp = s.d + a8, cm = s.d - a8;
     o[1] = cx + jx3;
     o[2] = cx - jx3;

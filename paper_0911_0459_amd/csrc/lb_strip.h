@@ -236,7 +236,11 @@ __device__ __forceinline__ void pull_lane(const Planes& q, const LaneCols& L, co
 template <typename Src>
 __device__ __forceinline__ float phi_delta(unsigned sm, float phi, float ux, float uy, float am, Src src) {
     auto adv = [](int i, float pp, float ax, float ay) {
-        const float eu = (float)ex_(i) * ax + (float)ey_(i) * ay;
+        // e_i.u with the unit components folded at compile time (0 * ay cannot
+        // be dropped by the compiler: it is not 0 for an infinite ay)
+        const int ex = ex_(i), ey = ey_(i);
+        const float t = ey == 0 ? ax : (ex == 0 ? ay : (ex == ey ? ax + ay : ax - ay));
+        const float eu = (ex < 0 || (ex == 0 && ey < 0)) ? -t : t;
         return pp * eu * (1.f + 1.5f * eu);
     };
     auto incoming = [&](int i) {

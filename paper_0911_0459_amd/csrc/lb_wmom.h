@@ -224,8 +224,8 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
             const PostState<CT> st8 = bin_node_state<CT, ST, FORCE>(c, mom_cur, sm_cur, phi, dx_cur, dy_cur, lap_cur);
             const int srow = row_info(g, y).y0 * md.rb;
             st(md, (float)st8.drho, L.b0, 0 * md.pb + srow);
-            st(md, (float)(st8.jx * (CT(1) / CT(3))), L.b0, 1 * md.pb + srow);
-            st(md, (float)(st8.jy * (CT(1) / CT(3))), L.b0, 2 * md.pb + srow);
+            st(md, (float)third(st8.jx), L.b0, 1 * md.pb + srow);
+            st(md, (float)third(st8.jy), L.b0, 2 * md.pb + srow);
             st(md, (float)st8.b, L.b0, 3 * md.pb + srow);
             st(md, (float)st8.d, L.b0, 4 * md.pb + srow);
             st(md, (float)st8.pxx, L.b0, 5 * md.pb + srow);

@@ -367,8 +367,11 @@ class Lattice:
         _check(_lib.lb_get_launch_config(self._h, C.byref(cfg)))
         return cfg
 
-    def set_launch_config(self, tile_rows=4, schedule=4, persist_blocks_per_cu=4, graph_steps=64, fp64_arith=1,
+    def set_launch_config(self, tile_rows=4, schedule=4, persist_blocks_per_cu=4, graph_steps=64, fp64_arith=None,
                           chunk_rows=8):
+        """fp64_arith None keeps the context's current arithmetic."""
+        if fp64_arith is None:
+            fp64_arith = self.launch_config().fp64_arith
         cfg = lb_launch_config(tile_rows, schedule, persist_blocks_per_cu, graph_steps, fp64_arith, chunk_rows)
         _check(_lib.lb_set_launch_config(self._h, C.byref(cfg)))
 

@@ -429,9 +429,9 @@ def test_autotune_keeps_state(L):
 
 def test_results_do_not_depend_on_earlier_tuning(L):
     """Two identical runs give the same bits whatever was tuned in between:
-    a tuning run in FP32 arithmetic on a lattice of the same size class leaves
-    the next context at the default shape and arithmetic, and applying the
-    tuned shape keeps the context's own arithmetic."""
+    a tuning run in the other arithmetic on a lattice of the same size class
+    leaves the next context at the default shape and arithmetic, and applying
+    the tuned shape keeps the context's own arithmetic."""
     w = small_binary(nx=260, ny=56, H=20, seed=61)
     p = L.params_from_workload(w, wall_grad=oracle_wall_grad(w))
     g = L.geometry_from_workload(w)
@@ -441,7 +441,7 @@ def test_results_do_not_depend_on_earlier_tuning(L):
     ref = first.moments()
     first.close()
     other = L.Lattice(p, g, w.initial_field())
-    other.set_launch_config(**dict(default, fp64_arith=0))
+    other.set_launch_config(**dict(default, fp64_arith=1 - default["fp64_arith"]))
     other.autotune(trial_steps=4)
     other.close()
     again = L.Lattice(p, g, w.initial_field())
