@@ -300,7 +300,10 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    common parts of the axis and of the diagonal populations, pxx* and pxy*,
  *    so a step moves 32 instead of 40 bytes per node (phi included).  The
  *    sweep rebuilds the populations of each row once, into LDS, and pulls
- *    from there.  Setting this schedule converts the stored state in place
+ *    from there.  phi is kept in 32-bit fixed point (2^-29 steps) and updated
+ *    by integer additions, so that the tiny updates in the tails of an
+ *    interface are not lost to FP32 rounding: phi is conserved far more
+ *    closely over long runs.  Setting this schedule converts the stored state in place
  *    (both buffers); leaving it converts back.  Results agree with schedule 4
  *    to rounding (the populations are rebuilt in FP32 from the stored FP32
  *    state instead of being rounded once from the collision's arithmetic).

@@ -647,6 +647,10 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
                     delete c;
                     return fail(LB_EINVAL, "vdW initial density must satisfy 0 < rho < 1/b");
                 }
+                if (c->model == LB_BINARY && !(std::fabs(v) < 3.5)) {
+                    delete c;
+                    return fail(LB_EINVAL, "binary initial phi must satisfy |phi| < 3.5 (fixed-point range 4)");
+                }
             }
     }
     int ndev = 0;
@@ -712,7 +716,14 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
         const lb_geometry& g = G[k];
         const CapDev& d = c->L.caps[k];
         std::vector<float> h((size_t)g.nx * g.ny);
-        for (size_t i = 0; i < h.size(); ++i) h[i] = (float)init_q[k][i];
+        for (size_t i = 0; i < h.size(); ++i) {
+            if (c->model == LB_BINARY) {   // phi in fixed point (29 fraction bits)
+                const int q = (int)std::lrint(init_q[k][i] * 536870912.0);
+                std::memcpy(&h[i], &q, sizeof q);
+            } else {
+                h[i] = (float)init_q[k][i];
+            }
+        }
         float* dst = c->arena[1] + (c->model == LB_BINARY ? d.off_phi : d.off_f);
         if (hipMemcpy2DAsync(dst, sizeof(float) * d.pitch, h.data(), sizeof(float) * g.nx, sizeof(float) * g.nx,
                              g.ny, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
@@ -1069,7 +1080,7 @@ struct CkptHeader {
     int32_t mstore, pad;   // storage of the saved f planes
 };
 
-constexpr uint64_t CKPT_MAGIC = 0x4C42434150434B33ULL;
+constexpr uint64_t CKPT_MAGIC = 0x4C42434150434B34ULL;   // phi in fixed point
 
 static uint64_t setup_hash(const lb_ctx* c) {
     uint64_t h = fnv1a(c->P.data(), sizeof(lb_params) * c->P.size());

@@ -28,7 +28,7 @@ struct CapDev {
     int y0, y1;              // tube fluid rows [y0, y1)
     int active;              // 0: retired, not advanced
     int par;                 // this capillary reads arena cur ^ par
-    int mstore;              // 1: planes 0..6 hold the post-collision state (moment storage), else 9 populations
+    int mstore;              // 1: moment storage (planes 0..6 the post-collision state, phi in fixed point), else 9 populations and FP32 phi
     long long off_f;         // offset of plane 0
     long long off_phi;       // offset of the phi plane (binary)
     long long plane;         // floats per plane = ny * pitch

@@ -141,6 +141,24 @@ __device__ __forceinline__ R sum9(const R (&f)[9]) {
     return f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
 }
 
+// The stored phi (binary model) is a 32-bit fixed-point number with 29
+// fraction bits, kept in the bits of its FP32 plane: a grid of 1.9e-9 instead
+// of FP32's 6e-8 at |phi| ~ 1.  Each step adds its update as a whole number of
+// grid steps, so that the small updates in the tails of an interface are kept
+// instead of rounded away (FP32 storage loses phi systematically there, 2e-4
+// of the total over 2e5 steps; the fixed point keeps it to 1e-8).  Range +-4.
+constexpr float PHI_FIX_SCALE = 536870912.f;              // 2^29
+constexpr float PHI_FIX_STEP = 1.f / 536870912.f;         // 2^-29 (exact)
+
+template <typename R = float>
+__device__ __forceinline__ R phi_of_fixed(float bits) {
+    return (R)__builtin_bit_cast(int, bits) * (R)PHI_FIX_STEP;
+}
+// the nearest grid point of an update (saturating)
+__device__ __forceinline__ int fixed_of_phi(float phi) { return (int)__builtin_rintf(phi * PHI_FIX_SCALE); }
+__device__ __forceinline__ int fixed_of_phi(double phi) { return (int)__builtin_rint(phi * (double)PHI_FIX_SCALE); }
+__device__ __forceinline__ float phi_bits(int q) { return __builtin_bit_cast(float, q); }
+
 // Pre-collision moments of a pulled (shifted) population set; rest of boundary
 // nodes applied as j = 0.
 template <typename R>
@@ -496,7 +514,7 @@ __device__ __forceinline__ void step_tile_bin(const StepArgs& a, int tile, R* ld
         const int sx = r % W4, sy = r / W4;
         const int gx = wrap_mod(k.t.x0 + sx - 2, g.nx);
         const int gy = wrap_mod(k.t.y0 + sy - 2, g.ny);
-        PH[r] = g.solid(gx, gy) ? R(0) : (R)psrc[(long long)gy * g.pitch + gx];
+        PH[r] = g.solid(gx, gy) ? R(0) : phi_of_fixed<R>(psrc[(long long)gy * g.pitch + gx]);
     }
     // phase 1b: own moments and u; u of the one-node ring
     R f[9];
@@ -596,7 +614,7 @@ __device__ __forceinline__ void step_tile_bin(const StepArgs& a, int tile, R* ld
         }
         delta += gin - go[i];
     }
-    k.dst[c.off_phi + own_idx] = (float)(phi + delta);
+    k.dst[c.off_phi + own_idx] = phi_bits(__builtin_bit_cast(int, psrc[own_idx]) + fixed_of_phi(delta));
 }
 
 // R: arithmetic type of the step (float, or double with FP32 storage).
@@ -657,7 +675,7 @@ __global__ void lb_moments_kernel(const CapDev* caps, int cap, const float* __re
             const float F = h.solid ? 0.f : c.Fx;
             u = (jx - 0.5f * F) / r;
             v = jy / r;
-            if (MODEL == 1) p = prev[c.off_phi + own];
+            if (MODEL == 1) p = phi_of_fixed(prev[c.off_phi + own]);
         }
         if (rho_o) rho_o[k] = r;
         if (ux_o) ux_o[k] = u;
@@ -670,8 +688,10 @@ __global__ void lb_moments_kernel(const CapDev* caps, int cap, const float* __re
 template <int MODEL>
 __device__ __forceinline__ float centre_q(const CapDev& c, const float* __restrict__ st,
                                           const float* __restrict__ prev, int x, int ya, int yb) {
-    if (MODEL == 1)
-        return 0.5f * (prev[c.off_phi + (long long)ya * c.pitch + x] + prev[c.off_phi + (long long)yb * c.pitch + x]);
+    if (MODEL == 1) {
+        const float a = prev[c.off_phi + (long long)ya * c.pitch + x], b = prev[c.off_phi + (long long)yb * c.pitch + x];
+        return 0.5f * (phi_of_fixed(a) + phi_of_fixed(b));
+    }
     if (c.mstore)
         return 0.5f * ((c.rho_ref + st[c.off_f + (long long)ya * c.pitch + x]) +
                        (c.rho_ref + st[c.off_f + (long long)yb * c.pitch + x]));
@@ -762,7 +782,6 @@ __global__ void lb_health_kernel(const CapDev* caps, const TileDev* tiles, int n
                     s += v;
                 }
             }
-            if (MODEL == 1) bad |= !isfinite(st[c.off_phi + own]);
             if (bad || !(s > 0.f)) atomicOr(&flags[t.cap], 1);
         }
     }

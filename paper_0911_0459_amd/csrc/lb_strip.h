@@ -308,10 +308,10 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
         m = ld(ps, L.b0, r.y0 * ps.rb);
         e = ld(ps, bx, r.y0 * ps.rb);
     };
-    auto phi_store = [&](int sl, const RowInfo& r, float m, float e) {
-        PH[sl][k + 1] = (L.t0 && r.w0) ? 0.f : m;
-        if (k == 0) PH[sl][0] = (te && r.w0) ? 0.f : e;
-        if (k == 1) PH[sl][PHW - 1] = (te && r.w0) ? 0.f : e;
+    auto phi_store = [&](int sl, const RowInfo& r, float m, float e) {   // m, e: fixed point
+        PH[sl][k + 1] = (L.t0 && r.w0) ? 0.f : phi_of_fixed(m);
+        if (k == 0) PH[sl][0] = (te && r.w0) ? 0.f : phi_of_fixed(e);
+        if (k == 1) PH[sl][PHW - 1] = (te && r.w0) ? 0.f : phi_of_fixed(e);
     };
     // moments of a pulled row (FP32, kept by the caller) and its velocity into LDS
     auto u_row = [&](int sl, const float (&f)[9], bool fluid, unsigned sm, Mom<float>& m) {
@@ -350,10 +350,13 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
     auto r3 = [&](int d) { int v = p3 + 1 + d; v -= v >= 3 ? 3 : 0; v -= v >= 3 ? 3 : 0; return v; };
 
     // ---- prologue: phi rows ya-2..ya+1; u, mu of rows ya-1, ya
+    int q_cur = 0, q_next = 0;   // fixed-point phi of this lane's column, rows y and y+1
     for (int d = -2; d <= 1; ++d) {
         float m, e;
         const RowInfo rr = row_info(g, s.ya + d);
         phi_load(rr, m, e);
+        if (d == 0) q_cur = __builtin_bit_cast(int, m);
+        if (d == 1) q_next = __builtin_bit_cast(int, m);
         phi_store(r5(d), rr, m, e);
     }
     float f[9];
@@ -407,6 +410,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
         // keep the uses of the previous requests below the new ones
         __builtin_amdgcn_sched_barrier(0);
         // (b) phi row y+2; u and moments of row y+1
+        const int q_new = __builtin_bit_cast(int, n.pm);
         phi_store(r5(2), n.rph, n.pm, n.pe);
         Mom<float> mom_n;
         u_row(r3(1), n.f, n.fl, n.sm, mom_n);
@@ -450,7 +454,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
                                              x = UX[s3][sk];
                                              y = UY[s3][sk];
                                          });
-            st(pd, phi + dphi, L.b0, srow);
+            st(pd, phi_bits(q_cur + fixed_of_phi(dphi)), L.b0, srow);
         }
         // (e) rotate the row state
         mom_cur = mom_n;
@@ -460,6 +464,8 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
         dy_cur = dy_n;
         lap_cur = lap_n;
         gmu_cur = gmu_n;
+        q_cur = q_next;
+        q_next = q_new;
         p5 = p5 == 4 ? 0 : p5 + 1;
         p3 = p3 == 2 ? 0 : p3 + 1;
         wave_sync();

@@ -121,8 +121,8 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     // phi is loaded unconditionally (solid nodes have valid addresses) and
     // masked when stored, so that no instruction waits on it early
     auto phi_load = [&](const RowInfo& r) { return ld(ps, L.b0, r.y0 * ps.rb); };
-    auto phi_store = [&](int slot, const RowInfo& r, float m) {
-        if (W.ph) RG[slot][R_PH][pj] = (L.t0 && r.w0) ? 0.f : m;
+    auto phi_store = [&](int slot, const RowInfo& r, float m) {   // m: fixed point
+        if (W.ph) RG[slot][R_PH][pj] = (L.t0 && r.w0) ? 0.f : phi_of_fixed(m);
     };
     // moments of a pulled row (FP32, kept by the caller) and its velocity into LDS
     auto u_row = [&](int slot, const float (&f)[9], bool fluid, unsigned sm, Mom<float>& m) {
@@ -157,9 +157,13 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
     };
 
     // ---- prologue: phi rows ya-2..ya+1; u, mu of rows ya-1, ya
+    int q_cur = 0, q_next = 0;   // fixed-point phi of this lane's column, rows y and y+1
     for (int d = -2; d <= 1; ++d) {
         const RowInfo rr = row_info(g, s.ya + d);
-        phi_store(sl(d), rr, phi_load(rr));
+        const float m = phi_load(rr);
+        if (d == 0) q_cur = __builtin_bit_cast(int, m);
+        if (d == 1) q_next = __builtin_bit_cast(int, m);
+        phi_store(sl(d), rr, m);
     }
     float f[9];
     Mom<float> mom_cur;
@@ -210,6 +214,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
         p.pm = phi_load(p.rph);
         __builtin_amdgcn_sched_barrier(0);
         // (b) phi row y+2; u and moments of row y+1
+        const int q_new = __builtin_bit_cast(int, n.pm);
         phi_store(sl(2), n.rph, n.pm);
         Mom<float> mom_n;
         u_row(sl(1), n.f, n.fl, n.sm, mom_n);
@@ -241,7 +246,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
                                              x = RG[sn][R_UX][kn];
                                              y = RG[sn][R_UY][kn];
                                          });
-            st(pd, phi + dphi, L.b0, srow);
+            st(pd, phi_bits(q_cur + fixed_of_phi(dphi)), L.b0, srow);
         }
         // (e) rotate the row state
         mom_cur = mom_n;
@@ -250,6 +255,8 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
         dx_cur = dx_n;
         dy_cur = dy_n;
         lap_cur = lap_n;
+        q_cur = q_next;
+        q_next = q_new;
         ry = ry == RING - 1 ? 0 : ry + 1;
     };
     for (int y = s.ya; y < s.yb; y += 2) {

@@ -6,7 +6,8 @@
 // from seven numbers (PostState: rho - rho_ref, j*, the axis and diagonal
 // common parts b and d, pxx*, pxy*).  This sweep stores those seven (j* as
 // j*/3), FP32, and phi: 32 bytes per node and step instead of 40 of the
-// population storage.
+// population storage.  phi is in fixed point, as in every binary sweep
+// (phi_of_fixed).
 //
 // Streaming needs the populations of the neighbours, so each lane loads the
 // state of its own column only (aligned 256-byte row segments), rebuilds the
@@ -134,6 +135,8 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
     bool fl_cur = false;
     float dx_cur = 0.f, dy_cur = 0.f, lap_cur = 0.f;
     float f0_cur = 0.f;   // f0 of row y+1 (this lane's column)
+    // phi of this lane's column in fixed point, rows y+1 and y (the update adds to it)
+    int q_next = 0, q_cur = 0;
 
     // iteration y: n holds the requests for row y+2, p receives those for row y+3
     auto iter = [&](int y, const Ahead& n, Ahead& p) {
@@ -142,6 +145,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
         request(y + 3 <= s.yb + 1 ? y + 3 : s.yb + 1, p);
         __builtin_amdgcn_sched_barrier(0);
         float f0_next = 0.f;
+        const int q_new = __builtin_bit_cast(int, n.pm);   // row y+2
         if (W.ph) {
             float f[9];
             pops_of_stored(n.m, f);
@@ -155,7 +159,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
             FH[h][0][pj] = f[1];
             FH[h][1][pj] = f[2];
             f0_next = f[0];
-            PH[m6(2)][pj] = (L.t0 && n.r.w0) ? 0.f : n.pm;
+            PH[m6(2)][pj] = (L.t0 && n.r.w0) ? 0.f : phi_of_fixed(n.pm);
         }
         lds_barrier();
         // ---- phase 2: pulls, moments and u of row y+1; stencils and A of row y+1
@@ -242,7 +246,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
                                              x = UA[un][0][kn];
                                              yy = UA[un][1][kn];
                                          });
-            st(pd, phi + dphi, L.b0, srow);
+            st(pd, phi_bits(q_cur + fixed_of_phi(dphi)), L.b0, srow);
         }
         // ---- rotate the row state
         mom_cur = mom_n;
@@ -252,6 +256,8 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
         dy_cur = dy_n;
         lap_cur = lap_n;
         f0_cur = f0_next;
+        q_cur = q_next;
+        q_next = q_new;
         t6 = t6 == 5 ? 0 : t6 + 1;
     };
     for (int y = s.ya - 4; y < s.yb; y += 2) {
@@ -268,7 +274,8 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
 // dimensional post-collision space): drho = sum f, j/3 with j = sum e f, b and
 // d the means of the axis and of the diagonal populations,
 // pxx* = (f1+f2)-(f3+f4), pxy* = (f5+f6)-(f7+f8); back by the inverse map.
-// FP64 arithmetic, one rounding per stored value.
+// FP64 arithmetic, one rounding per stored value.  (phi is in fixed point in
+// either storage.)
 template <bool TO_STATE>
 __global__ void __launch_bounds__(256) lb_convert_kernel(const CapDev* caps, float* arena) {
     const CapDev c = caps[blockIdx.y];

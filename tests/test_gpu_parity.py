@@ -493,7 +493,8 @@ def test_moments_device_matches_host(L):
         assert np.array_equal(d.cpu().numpy().reshape(h.shape).astype(np.float64), h)
 
 
-def test_throughput_runs_follow_the_filling_balance(L):
+@pytest.mark.parametrize("cfg", [None, dict(schedule=6, chunk_rows=20)], ids=["populations", "moment-storage"])
+def test_throughput_runs_follow_the_filling_balance(L, cfg):
     """The six 4096x256 throughput runs (ratios 1, 10, 100 x 30 and 60 degrees)
     at their real size and length (200000 steps), batched: over the second half
     of each run the filling obeys the capillary balance of Eq. 1 and Eq. 3 with
@@ -504,6 +505,8 @@ def test_throughput_runs_follow_the_filling_balance(L):
     works = I.throughput_runs()
     P = [L.params_from_workload(w) for w in works]
     lat = L.Lattice(P, [L.geometry_from_workload(w) for w in works], [w.initial_field() for w in works])
+    if cfg is not None:
+        lat.set_launch_config(**cfg)
     m0 = [lat.moments(k) for k in range(len(works))]
     every, steps = 2000, works[0].steps
     lat.step(steps, sample_every=every)
@@ -515,11 +518,15 @@ def test_throughput_runs_follow_the_filling_balance(L):
         assert len(t) == steps // every
         rho, _, _, phi = lat.moments(k)
         assert abs(rho[fluid].sum() - m0[k][0][fluid].sum()) / m0[k][0][fluid].sum() < 1e-5
-        # phi is stored in FP32: each step rounds phi + dphi to the FP32 grid
-        # (half an ulp, 6e-8 at |phi| ~ 1), and while an interface sweeps a node the
-        # roundings do not average out.  The budget of 1e-5 per 1e4 steps, scaled
-        # to 2e5 steps and doubled, is 4e-4 (the FP64 oracle conserves to 1e-12).
-        assert abs(phi[fluid].sum() - m0[k][3][fluid].sum()) / np.abs(m0[k][3][fluid]).sum() < 4e-4
+        # phi is stored in fixed point on a 2^-29 grid and each step adds its
+        # update as a whole number of grid steps.  Stored in FP32 (half an ulp,
+        # 6e-8 at |phi| ~ 1) the small updates in the tails of an interface were
+        # rounded away, and these runs lost up to 2.7e-4 of their phi; the
+        # budget is now 1e-5 for the whole run (the FP64 oracle conserves to
+        # 1e-12).
+        drift = abs(phi[fluid].sum() - m0[k][3][fluid].sum()) / np.abs(m0[k][3][fluid]).sum()
+        print(f"{'populations' if cfg is None else 'moment storage'} run {k}: relative phi drift {drift:.3e}")
+        assert drift < 1e-5
         half = t >= steps // 2
         Ltot = w.geom.tube_len + 0.5 * w.geom.tube_h
         q = 0.5 * (w.nu_l - w.nu_g) * le[half] ** 2 + w.nu_g * Ltot * le[half]
