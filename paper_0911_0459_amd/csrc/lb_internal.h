@@ -18,7 +18,10 @@ constexpr int TILE_W = 64;  // tile width along x = one wavefront
 //
 // Stored per capillary and arena, each plane ny x pitch floats:
 //   planes 0..8   s_i = f_i - r_i, the shifted post-collision populations
-//   plane  9      phi (binary only): the order parameter
+//                 (moment storage, binary: planes 0..6 hold the seven numbers
+//                 that fix them instead, see lb_wmom.h)
+//   plane  9      phi (binary only): the order parameter, in 32-bit fixed point
+//                 (29 fraction bits) in the plane's bits
 // A step reads arena `cur ^ par` and writes the other one.  After step t the
 // read-from arena of the next step holds f*(t) and phi(t+1), and the other
 // arena's plane 9 still holds phi(t).
@@ -28,7 +31,7 @@ struct CapDev {
     int y0, y1;              // tube fluid rows [y0, y1)
     int active;              // 0: retired, not advanced
     int par;                 // this capillary reads arena cur ^ par
-    int mstore;              // 1: moment storage (planes 0..6 the post-collision state, phi in fixed point), else 9 populations and FP32 phi
+    int mstore;              // 1: moment storage (planes 0..6 hold the post-collision state), else 9 populations
     long long off_f;         // offset of plane 0
     long long off_phi;       // offset of the phi plane (binary)
     long long plane;         // floats per plane = ny * pitch

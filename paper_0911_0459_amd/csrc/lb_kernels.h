@@ -25,8 +25,9 @@
 // source), which the kernel evaluates from phi, u and mu of the node and its
 // eight neighbours: phi is read with a two-node halo (the neighbours' mu needs
 // their Laplacian) and u of the one-node halo comes from the neighbours' own
-// pulled populations.  The update is formed as phi(t) plus the sum of the
-// small differences g^eq_i(r - e_i) - g^eq_i(r), so it is rounded once.
+// pulled populations.  The update is formed as the sum of the small
+// differences g^eq_i(r - e_i) - g^eq_i(r) and added to the stored phi(t), a
+// fixed-point number (phi_of_fixed), as a whole number of grid steps.
 //
 // Populations are SoA FP32 planes [9][ny][pitch], x fastest, pitch a multiple
 // of 64 floats; one wavefront covers one 64-wide row segment, so every load and
