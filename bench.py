@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -47,12 +48,20 @@ def stored_bytes_per_lup(model: str, schedule: int) -> int:
 KERNEL_SOURCES = ("lb_internal.h", "lb_kernels.h", "lb_strip.h", "lb_strip_table.h", "lb_wide.h", "lb_wide2.h", "lb_wmom.h")
 
 
+def code_of(text: str) -> str:
+    """C++ source without its comments and blank space, so that editing a
+    comment does not count as a change of the kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources of the step kernels (the counter summary in
-    profiles/ is only used while it matches)."""
+    """Hash of the code of the step kernels (the counter summary in profiles/
+    is only used while it matches)."""
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_0911_0459_amd", "csrc", name), "rb").read())
+        h.update(code_of(open(os.path.join(ROOT, "paper_0911_0459_amd", "csrc", name)).read()).encode())
     return h.hexdigest()[:16]
 
 

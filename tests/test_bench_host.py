@@ -74,3 +74,13 @@ def test_algorithmic_and_stored_bytes():
     assert bench.stored_bytes_per_lup("vdw", 5) == 72
     assert bench.stored_bytes_per_lup("binary", 4) == 80
     assert bench.stored_bytes_per_lup("binary", 6) == 64
+
+
+def test_kernel_hash_ignores_comments_only():
+    """The counter summaries are tied to the kernels' code: editing a comment
+    keeps them, changing code drops them."""
+    a = "int f(int x) { // one\n  return x + 1; /* two\n lines */ }\n"
+    b = "int f(int x) {\n  // another comment\n  return x + 1;\n}\n"
+    c = "int f(int x) { return x + 2; }"
+    assert bench.code_of(a) == bench.code_of(b)
+    assert bench.code_of(a) != bench.code_of(c)
