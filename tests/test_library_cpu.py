@@ -130,3 +130,24 @@ def test_state_bytes(L):
     arenas = 2 * 10 * 30 * 128 * 4
     assert arenas <= nb <= arenas + (1 << 20)
     assert L.lb_state_bytes(p, L.make_geometry(100, 30, 40, 70, 10, 10)) == 0
+
+
+def test_binary_initial_phi_outside_the_fixed_point_range_is_refused(L):
+    """phi is stored in 32-bit fixed point with range +-4: an initial field
+    with |phi| >= 3.5 is refused before any device work (LB_EINVAL)."""
+    nx, ny = 20, 10
+    q = np.ones((ny, nx))
+    q[2, 2] = 3.6
+    p = L.make_params("binary", kappa=0.04, A=0.04, B=0.04, nu_l=0.5, nu_g=0.05, wall_grad=0.0)
+    assert _lib_init_code(L, p, L.make_geometry(nx=nx, ny=ny), q) == L.LB_EINVAL
+    assert "phi" in L._lib.lb_last_error().decode()
+
+
+def test_context_calls_refuse_a_null_context(L):
+    """Entry points on a context check it before touching a device."""
+    import ctypes as C
+    cfg = L.lb_launch_config(4, 6, 4, 64, 0, 20)
+    assert L._lib.lb_set_launch_config(None, C.byref(cfg)) == L.LB_EINVAL
+    assert L._lib.lb_set_wall_gradient(None, 0, C.c_double(-0.1)) == L.LB_EINVAL
+    found = C.c_int(7)
+    assert L._lib.lb_use_tuned_launch_config(None, C.byref(found)) == L.LB_EINVAL
