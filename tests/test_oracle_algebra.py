@@ -139,6 +139,50 @@ def test_collision_relaxes_moments_with_rates_S(seed):
         assert np.abs(collide(VDW, f2, fe, omega, 0.0, 0.0) - fs).max() < 1e-14
 
 
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("model", ["vdw", "binary"])
+def test_post_collision_state_is_fixed_by_seven_numbers(model, seed):
+    """With the rates of Appendix A (e, eps, qx, qy relaxed fully) and the
+    equilibrium's q^eq = -j, the post-collision populations are fixed by seven
+    numbers: rho, j*, the means b and d of the axis and of the diagonal
+    populations, and the stresses pxx*, pxy*.  This is what the moment
+    storage keeps.  From those seven, each axis population is
+    b +- pxx*/4 +- j*/3 and each diagonal one d +- pxy*/4 +- (jx* +- jy*)/12,
+    and the oracle's f* is recovered to rounding; a pre-collision state with
+    other non-hydrodynamic moments gives the same seven numbers."""
+    rng = np.random.default_rng(500 + seed)
+    p = VDW if model == "vdw" else BIN
+    rho = rng.uniform(2.6, 4.5) if model == "vdw" else rng.uniform(0.95, 1.05)
+    u = rng.uniform(-0.05, 0.05, 2)
+    dq = rng.uniform(-0.3, 0.3, 2)
+    omega = rng.uniform(0.6, 1.8)
+    X = rng.uniform(0.2, 1.0)
+    fe = feq(p, rho, u[0], u[1], omega, X, dq[0], dq[1])
+    M = matrix_M()
+    # a pre-collision state with the equilibrium's conserved moments and
+    # arbitrary e, eps, qx, qy, pxx, pxy
+    dm = rng.normal(0, 0.01, 9)
+    dm[[0, 3, 5]] = 0.0
+    f = fe + np.linalg.solve(M, dm)
+    fs = collide(p, f, fe, omega, u[0], u[1])
+    ms = M @ fs
+    assert abs(ms[4] + ms[3]) < 1e-15 and abs(ms[6] + ms[5]) < 1e-15   # qx* = -jx*, qy* = -jy*
+    drho, jx, jy = fs.sum(), E[:, 0] @ fs, E[:, 1] @ fs
+    b, d = fs[1:5].mean(), fs[5:9].mean()
+    pxx, pxy = (fs[1] + fs[2]) - (fs[3] + fs[4]), (fs[5] + fs[6]) - (fs[7] + fs[8])
+    ax, dg = pxx / 4, pxy / 4
+    rebuilt = np.array([drho - 4 * (b + d),
+                        b + ax + jx / 3, b + ax - jx / 3, b - ax + jy / 3, b - ax - jy / 3,
+                        d + dg + (jx + jy) / 12, d + dg - (jx + jy) / 12,
+                        d - dg - (jx - jy) / 12, d - dg + (jx - jy) / 12])
+    assert np.abs(rebuilt - fs).max() < 1e-15
+    # the seven numbers do not see the non-hydrodynamic moments of f
+    dm2 = np.zeros(9)
+    dm2[[1, 2, 4, 6]] = rng.normal(0, 0.02, 4)
+    fs2 = collide(p, f + np.linalg.solve(M, dm2), fe, omega, u[0], u[1])
+    assert np.abs(fs2 - fs).max() < 1e-15
+
+
 def test_guo_forcing_momentum_and_mass():
     """Guo et al. (2002): the forcing adds F to the momentum and no mass;
     with u = (j + F/2)/rho the second moment gains u F + F u (1 - omega/2)
