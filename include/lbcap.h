@@ -109,8 +109,11 @@ size_t lb_state_bytes(const lb_params* p, const lb_geometry* g);
  *    bytes, 256-byte aligned (e.g. from PyTorch); NULL lets the library allocate.
  *  hip_stream: hipStream_t to enqueue on; NULL creates a library-owned stream.
  * Validation: 0 < omega < 2 for every viscosity, 0 < b rho < 1 for vdW,
- * finite values, H >= 3, 1 <= y0, y0 + H <= ny - 1, x_in + tube_len <= nx,
- * Gamma >= 0.  Errors: LB_EINVAL, LB_ENOMEM, LB_EDEVICE. */
+ * |phi| < 3.5 for the binary model (phi is stored as a 32-bit fixed-point
+ * number with 29 fraction bits, range 4, so that the small updates in the
+ * tails of an interface are kept), finite values, H >= 3, 1 <= y0,
+ * y0 + H <= ny - 1, x_in + tube_len <= nx, Gamma >= 0.
+ * Errors: LB_EINVAL, LB_ENOMEM, LB_EDEVICE. */
 lb_status lb_init(lb_ctx** out, const lb_params* p, const lb_geometry* g, const double* init_q,
                   void* d_state, size_t bytes, void* hip_stream);
 
@@ -284,7 +287,7 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    output columns marching along y through chunks of chunk_rows rows (0: the
  *    whole height), strips grouped so that each of the 8 XCDs works on a
  *    contiguous run of them; every population row is read once per step.
- *    4 (default) the same row sweep with a workgroup per strip of 192 output columns
+ *    4 (the van der Waals model's default) the same row sweep with a workgroup per strip of 192 output columns
  *    aligned to the row pitch (three wavefronts of 64 output columns and one
  *    that supplies the two neighbour columns), so that no stored cache line is
  *    shared between workgroups.  The same arithmetic as 3, compiled apart:
@@ -294,17 +297,15 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    nodes, keeps the intermediate step in LDS and writes the second step, so
  *    that the populations cross HBM once per two steps; an odd step count
  *    ends with one launch of schedule 4.  The same arithmetic per step.
- *    6 (binary model only) the strips of 4 over a stored state of seven FP32
+ *    6 (binary model only; its default) the strips of 4 over a stored state of seven FP32
  *    planes instead of nine populations: with the rates of Appendix A the
  *    post-collision populations of a node follow from rho - rho_ref, j* / 3, the
  *    common parts of the axis and of the diagonal populations, pxx* and pxy*,
  *    so a step moves 32 instead of 40 bytes per node (phi included).  The
  *    sweep rebuilds the populations of each row once, into LDS, and pulls
- *    from there.  phi is kept in 32-bit fixed point (2^-29 steps) and updated
- *    by integer additions, so that the tiny updates in the tails of an
- *    interface are not lost to FP32 rounding: phi is conserved far more
- *    closely over long runs.  Setting this schedule converts the stored state in place
- *    (both buffers); leaving it converts back.  Results agree with schedule 4
+ *    from there.  Setting this schedule converts the stored state in place
+ *    (both buffers); leaving it converts back (a context of the binary model
+ *    starts in it).  Results agree with schedule 4
  *    to rounding (the populations are rebuilt in FP32 from the stored FP32
  *    state instead of being rounded once from the collision's arithmetic).
  *    0..2 tiles of 64 x tile_rows nodes with the order field recomputed on a
@@ -312,7 +313,7 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    2 persistent workgroups (persist_blocks_per_cu x 256 CUs) striding the table.
  *  tile_rows: rows per tile for schedules 0..2 (1, 2, 4 or 8).
  *  chunk_rows: target rows per strip chunk for schedules 3..6 (0, or 4..4096;
- *    default 8): each strip column is cut into chunks of about that height that
+ *    default 8 for the van der Waals model, 20 for the binary one): each strip column is cut into chunks of about that height that
  *    start an even number of rows apart, so that the results do not depend on it.
  *    From 12 rows on, the last rows of the last columns of each XCD's run go to
  *    short chunks (a quarter of the height, at least 4 rows) that end the step.

@@ -707,6 +707,12 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
         hipMemsetAsync(c->d_flags, 0, sizeof(int) * n, c->stream) != hipSuccess ||
         hipMemsetAsync(c->d_lnow, 0, sizeof(float) * n, c->stream) != hipSuccess)
         return bail(fail(LB_EDEVICE, "upload of descriptors failed"));
+    // default launch shape: the moment storage for the binary model (its
+    // fastest sweep), the wide population sweep for van der Waals
+    if (c->model == LB_BINARY) {
+        c->cfg.schedule = 6;
+        c->cfg.chunk_rows = 20;
+    }
     s = upload_tiles(c);
     if (s) return bail(s);
     // initial fields go to arena 1 as FP32 planes (pitched): the phi plane for
@@ -738,6 +744,8 @@ lb_status create(lb_ctx** out, int n, const lb_params* P, const lb_geometry* G, 
         return bail(fail(LB_EDEVICE, "initialisation kernel failed"));
     c->cur = 0;
     c->t = 0;
+    // the initialisation writes populations; the moment storage converts them
+    if (lb_status s2 = set_storage(c, c->cfg.schedule == 6 ? 1 : 0)) return bail(s2);
     *out = c;
     return LB_OK;
 }

@@ -69,7 +69,7 @@ def test_binary_capillary_1e4_steps(L):
     """Binary capillary (ratio 10, 60 degrees) on a 256x64 lattice."""
     w = small_binary()
     orc, lo = run_oracle(w, 10_000, sample_every=500)
-    for cfg in (None, dict(schedule=6, chunk_rows=12)):   # population and moment storage
+    for cfg in (dict(schedule=4, chunk_rows=8), None):   # population storage; the default, moment storage
         gpu, lg = gpu_run(L, w, 10_000, sample_every=500, cfg=cfg)
         drho, dphi, du = field_errors(w, gpu, orc)
         print(f"binary 1e4 {cfg}: max rel drho {drho:.3e}, max dphi {dphi:.3e}, du {du:.3e}, "
@@ -81,13 +81,13 @@ def test_binary_capillary_1e4_steps(L):
 def test_binary_capillary_1024x128_1e4_steps(L):
     """The binary capillary at its real size: 1024x128, tube H=40 and length
     768, ratio 10, 60 degrees, seed 2, 10^4 steps against the oracle in the
-    default launch shape and in the moment storage (schedule 6), the filled
-    length compared every 500 steps."""
+    population storage (schedule 4) and in the default launch shape (the
+    moment storage, schedule 6), the filled length compared every 500 steps."""
     w = I.binary_capillary_1024x128()
     print(f"binary 1024x128 1e4: oracle run", flush=True)
     orc, lo = run_oracle(w, 10_000, sample_every=500)
     assert lo[-1] > lo[0] + 5.0          # the liquid is filling the tube
-    for cfg in (None, dict(schedule=6, chunk_rows=12)):   # population and moment storage
+    for cfg in (dict(schedule=4, chunk_rows=8), None):   # population storage; the default, moment storage
         print(f"binary 1024x128 1e4: GPU run {cfg}", flush=True)
         gpu, lg = gpu_run(L, w, 10_000, sample_every=500, cfg=cfg)
         drho, dphi, du = field_errors(w, gpu, orc)
@@ -339,7 +339,8 @@ def test_checkpoint_resume_is_bitwise(L):
         other.load(blob)
 
 
-def test_batch_equals_single_runs_and_oracle(L):
+@pytest.mark.parametrize("cfg", [dict(schedule=4, chunk_rows=8), None], ids=["populations", "default"])
+def test_batch_equals_single_runs_and_oracle(L, cfg):
     """Uneven capillaries advanced together give bitwise the single-run result."""
     ws = [I.sweep_capillary(77, k, steps=0) for k in range(3)]
     # shrink the draws so the oracle stays fast
@@ -351,9 +352,13 @@ def test_batch_equals_single_runs_and_oracle(L):
     G = [L.geometry_from_workload(w) for w in ws]
     Q = [w.initial_field() for w in ws]
     batch = L.Lattice(P, G, Q)
+    if cfg is not None:
+        batch.set_launch_config(**cfg)
     batch.step(250, sample_every=50)
     for k, w in enumerate(ws):
         single = L.Lattice(P[k], G[k], Q[k])
+        if cfg is not None:
+            single.set_launch_config(**cfg)
         single.step(250)
         for x, y in zip(batch.moments(k), single.moments()):
             assert np.array_equal(x, y)
@@ -367,11 +372,15 @@ def test_batch_equals_single_runs_and_oracle(L):
 
 
 def test_retire_freezes_and_revive_resumes(L):
+    """Population storage (the moment storage's own test is in
+    test_gpu_moment_storage.py)."""
+    S4 = dict(schedule=4, chunk_rows=8)
     ws = [small_binary(nx=160, ny=40, H=12, seed=s) for s in (31, 32)]
     P = [L.params_from_workload(w, wall_grad=oracle_wall_grad(w)) for w in ws]
     G = [L.geometry_from_workload(w) for w in ws]
     Q = [w.initial_field() for w in ws]
     b = L.Lattice(P, G, Q)
+    b.set_launch_config(**S4)
     b.step(101)
     frozen = b.moments(1)
     b.retire(1)
@@ -381,10 +390,12 @@ def test_retire_freezes_and_revive_resumes(L):
     b.revive(1)
     b.step(99)
     ref = L.Lattice(P[1], G[1], Q[1])
+    ref.set_launch_config(**S4)
     ref.step(200)
     for x, y in zip(ref.moments(), b.moments(1)):
         assert np.array_equal(x, y)
     ref0 = L.Lattice(P[0], G[0], Q[0])
+    ref0.set_launch_config(**S4)
     ref0.step(251)
     for x, y in zip(ref0.moments(), b.moments(0)):
         assert np.array_equal(x, y)
@@ -493,7 +504,7 @@ def test_moments_device_matches_host(L):
         assert np.array_equal(d.cpu().numpy().reshape(h.shape).astype(np.float64), h)
 
 
-@pytest.mark.parametrize("cfg", [None, dict(schedule=6, chunk_rows=20)], ids=["populations", "moment-storage"])
+@pytest.mark.parametrize("cfg", [dict(schedule=4, chunk_rows=12), None], ids=["populations", "moment-storage"])
 def test_throughput_runs_follow_the_filling_balance(L, cfg):
     """The six 4096x256 throughput runs (ratios 1, 10, 100 x 30 and 60 degrees)
     at their real size and length (200000 steps), batched: over the second half
@@ -525,7 +536,7 @@ def test_throughput_runs_follow_the_filling_balance(L, cfg):
         # budget is now 1e-5 for the whole run (the FP64 oracle conserves to
         # 1e-12).
         drift = abs(phi[fluid].sum() - m0[k][3][fluid].sum()) / np.abs(m0[k][3][fluid]).sum()
-        print(f"{'populations' if cfg is None else 'moment storage'} run {k}: relative phi drift {drift:.3e}")
+        print(f"{'moment storage' if cfg is None else 'populations'} run {k}: relative phi drift {drift:.3e}")
         assert drift < 1e-5
         half = t >= steps // 2
         Ltot = w.geom.tube_len + 0.5 * w.geom.tube_h
