@@ -364,10 +364,13 @@ lb_status convert_arena(lb_ctx* c, int b, int to_state) {
     long long most = 0;
     for (const CapDev& d : c->L.caps) most = std::max(most, d.plane);
     const int gx = (int)std::min<long long>((most + 255) / 256, 1024);
+    const int gy = std::min(c->n, 65535);   // the kernel strides over further capillaries
     if (to_state)
-        hipLaunchKernelGGL(lb_convert_kernel<true>, dim3(gx, c->n), dim3(256), 0, c->stream, c->d_caps, c->arena[b]);
+        hipLaunchKernelGGL(lb_convert_kernel<true>, dim3(gx, gy), dim3(256), 0, c->stream, c->d_caps, c->n,
+                           c->arena[b]);
     else
-        hipLaunchKernelGGL(lb_convert_kernel<false>, dim3(gx, c->n), dim3(256), 0, c->stream, c->d_caps, c->arena[b]);
+        hipLaunchKernelGGL(lb_convert_kernel<false>, dim3(gx, gy), dim3(256), 0, c->stream, c->d_caps, c->n,
+                           c->arena[b]);
     HIP_TRY(hipGetLastError());
     return LB_OK;
 }

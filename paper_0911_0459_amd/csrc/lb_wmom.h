@@ -267,7 +267,8 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
     }
 }
 
-// In-place conversion of one arena's f regions (every capillary, blockIdx.y)
+// In-place conversion of one arena's f regions (every capillary: blockIdx.y
+// strides over them)
 // between the nine populations and the seven-plane post-collision state: the
 // library switches the storage when a launch configuration of the other
 // storage is set.  From populations (which a step leaves in the seven-
@@ -277,32 +278,34 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
 // FP64 arithmetic, one rounding per stored value.  (phi is in fixed point in
 // either storage.)
 template <bool TO_STATE>
-__global__ void __launch_bounds__(256) lb_convert_kernel(const CapDev* caps, float* arena) {
-    const CapDev c = caps[blockIdx.y];
-    float* base = arena + c.off_f;
-    for (long long k = blockIdx.x * 256LL + threadIdx.x; k < c.plane; k += 256LL * gridDim.x) {
-        float* p = base + k;
-        if (TO_STATE) {
-            double f[9];
+__global__ void __launch_bounds__(256) lb_convert_kernel(const CapDev* caps, int ncaps, float* arena) {
+    for (int cap = blockIdx.y; cap < ncaps; cap += gridDim.y) {
+        const CapDev c = caps[cap];
+        float* base = arena + c.off_f;
+        for (long long k = blockIdx.x * 256LL + threadIdx.x; k < c.plane; k += 256LL * gridDim.x) {
+            float* p = base + k;
+            if (TO_STATE) {
+                double f[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) f[i] = p[i * c.plane];
-            const double ax = (f[1] + f[2]), ay = (f[3] + f[4]), dp = (f[5] + f[6]), dm = (f[7] + f[8]);
-            const float m[NMOM] = {(float)(f[0] + ((ax + ay) + (dp + dm))),
-                                   (float)((((f[1] - f[2]) + (f[5] - f[6])) + (f[8] - f[7])) / 3.0),
-                                   (float)((((f[3] - f[4]) + (f[5] - f[6])) + (f[7] - f[8])) / 3.0),
-                                   (float)(0.25 * (ax + ay)),
-                                   (float)(0.25 * (dp + dm)),
-                                   (float)(ax - ay),
-                                   (float)(dp - dm)};
+                for (int i = 0; i < 9; ++i) f[i] = p[i * c.plane];
+                const double ax = (f[1] + f[2]), ay = (f[3] + f[4]), dp = (f[5] + f[6]), dm = (f[7] + f[8]);
+                const float m[NMOM] = {(float)(f[0] + ((ax + ay) + (dp + dm))),
+                                       (float)((((f[1] - f[2]) + (f[5] - f[6])) + (f[8] - f[7])) / 3.0),
+                                       (float)((((f[3] - f[4]) + (f[5] - f[6])) + (f[7] - f[8])) / 3.0),
+                                       (float)(0.25 * (ax + ay)),
+                                       (float)(0.25 * (dp + dm)),
+                                       (float)(ax - ay),
+                                       (float)(dp - dm)};
 #pragma unroll
-            for (int i = 0; i < NMOM; ++i) p[i * c.plane] = m[i];
-        } else {
-            double m[NMOM], o[9];
+                for (int i = 0; i < NMOM; ++i) p[i * c.plane] = m[i];
+            } else {
+                double m[NMOM], o[9];
 #pragma unroll
-            for (int i = 0; i < NMOM; ++i) m[i] = p[i * c.plane];
-            pops_of_state(PostState<double>{m[0], 3.0 * m[1], 3.0 * m[2], m[3], m[4], m[5], m[6]}, o);
+                for (int i = 0; i < NMOM; ++i) m[i] = p[i * c.plane];
+                pops_of_state(PostState<double>{m[0], 3.0 * m[1], 3.0 * m[2], m[3], m[4], m[5], m[6]}, o);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) p[i * c.plane] = (float)o[i];
+                for (int i = 0; i < 9; ++i) p[i * c.plane] = (float)o[i];
+            }
         }
     }
 }
