@@ -189,3 +189,31 @@ def test_moment_storage_is_refused_for_the_vdw_model(L):
     assert e.value.code == L.LB_EINVAL
     assert lat.launch_config().schedule == 4
     lat.close()
+
+
+def test_full_sweep_in_the_bench_shape_matches_oracle_on_sampled_capillaries(L):
+    """The benchmark's workload at its full size (the 256 uneven capillaries of
+    the sweep, 32.95 M fluid nodes) in the launch shape the bench times
+    (moment storage, chunks of 20 rows, 64-step graphs), sampled: after 400
+    steps the two smallest capillaries, a middle one and the largest agree
+    with the oracle run on each alone, at the short-run tolerances, and their
+    filled lengths, sampled every 100 steps, within 0.05."""
+    ws = I.sweep_batch(4, 256)
+    lat = L.Lattice([L.params_from_workload(w) for w in ws], [L.geometry_from_workload(w) for w in ws],
+                    [w.initial_field() for w in ws])
+    lat.set_launch_config(schedule=6, chunk_rows=20, graph_steps=64)
+    lat.step(400, sample_every=100)
+    lat.check()
+    fluid = [int((~w.geom.solid()).sum()) for w in ws]
+    order = np.argsort(fluid)
+    picks = [int(order[0]), int(order[1]), int(order[len(order) // 2]), int(order[-1])]
+    for k in picks:
+        w = ws[k]
+        print(f"sweep capillary {k}: {w.geom.nx}x{w.geom.ny}, H {w.geom.tube_h}, {fluid[k]} fluid nodes", flush=True)
+        orc, lo = run_oracle(w, 400, sample_every=100)
+        drho, dphi, du = field_errors(w, lat.moments(k), orc)
+        steps, lg = lat.l_history(k)
+        assert list(steps) == [100, 200, 300, 400]
+        assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (k, drho, dphi, du)
+        assert np.abs(lg - lo).max() < 0.05, (k, lg, lo)
+    lat.close()
