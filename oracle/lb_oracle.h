@@ -7,6 +7,12 @@
  * written to check the GPU library against.  Only the test suite, the smoke
  * check and the benchmark's CPU-baseline leg may load it; the product path never
  * does.  It shares no code, header, table or constant with the GPU library.
+ *
+ * Parity unpinned: which ghost a node at a convex lip of the tube takes in the
+ * wall rule of the stencils (through the node; the paper does not say, and no
+ * symmetry or closed form fixes it; the flat-wall gradient and the mirror
+ * symmetry of the two lips are pinned).  orc_set_wall_gradient only replaces
+ * the gradient the following steps use.
  */
 #ifndef LB_ORACLE_H
 #define LB_ORACLE_H
