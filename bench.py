@@ -37,11 +37,15 @@ BYTES_PER_LUP = {"vdw": 72, "binary": 80}
 BYTES_PER_LUP_MOMENT_STORAGE = 64            # schedule 6 (binary): 7 state planes + phi, read and written
 
 
-def stored_bytes_per_lup(model: str, schedule: int) -> int:
+def stored_bytes_per_lup(model: str, schedule: int) -> float:
     """Bytes per fluid-node update that the launch shape's own storage must
-    move: the method's figure, or 64 B for the binary moment storage, which
-    stores the seven numbers that fix the post-collision populations."""
-    return BYTES_PER_LUP_MOMENT_STORAGE if (model == "binary" and schedule == 6) else BYTES_PER_LUP[model]
+    move: the method's figure; 64 B for the binary moment storage, which
+    stores the seven numbers that fix the post-collision populations; half the
+    method's figure with two time steps per sweep, which reads and writes the
+    populations once per two updates."""
+    if model == "binary" and schedule == 6:
+        return BYTES_PER_LUP_MOMENT_STORAGE
+    return BYTES_PER_LUP[model] / 2 if schedule == 5 else BYTES_PER_LUP[model]
 
 
 # the step kernels and the strip table that shapes their traffic

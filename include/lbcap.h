@@ -292,11 +292,13 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    that supplies the two neighbour columns), so that no stored cache line is
  *    shared between workgroups.  The same arithmetic as 3, compiled apart:
  *    the results agree to the last bits (vdW bitwise, binary within 3e-7).
- *    5 (van der Waals model only) the strips of 4, each launch advancing two
- *    time steps: the sweep reads the populations once with a halo of three
- *    nodes, keeps the intermediate step in LDS and writes the second step, so
- *    that the populations cross HBM once per two steps; an odd step count
- *    ends with one launch of schedule 4.  The same arithmetic per step.
+ *    5 the strips of 4, each launch advancing two time steps: the sweep
+ *    reads the populations (and phi) once with a halo of three nodes (binary
+ *    model: four), keeps the intermediate step in LDS and writes the second
+ *    step, so that the populations cross HBM once per two steps; an odd step
+ *    count ends with one launch of schedule 4.  The same arithmetic per step
+ *    as schedule 4 (the intermediate step rounded to FP32, phi to its fixed
+ *    point, as a single step stores them).
  *    6 (binary model only; its default) the strips of 4 over a stored state of seven FP32
  *    planes instead of nine populations: with the rates of Appendix A the
  *    post-collision populations of a node follow from rho - rho_ref, j* / 3, the

@@ -464,7 +464,9 @@ void launch_strip_f(lb_ctx* c, const StripArgs& a, int grid, bool fused) {
         else
             hipLaunchKernelGGL((lb_strip_vdw<CT, FORCE>), dim3(grid), dim3(SW), 0, c->stream, a);
     } else {
-        if (c->cfg.schedule == 6)
+        if (fused)
+            hipLaunchKernelGGL((lb_wide2_bin<MT, CT, ST, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
+        else if (c->cfg.schedule == 6)
             hipLaunchKernelGGL((lb_wmom_bin<MT, CT, ST, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
         else if (wide)
             hipLaunchKernelGGL((lb_wide_bin<MT, CT, ST, FORCE>), dim3(grid), dim3(WIDE_THREADS), 0, c->stream, a);
@@ -582,9 +584,16 @@ lb_status prepare_graphs(lb_ctx* c, long n) {
     return LB_OK;
 }
 
-lb_status run_steps(lb_ctx* c, long n) {
+// readable: leave the state as the read-outs expect it.  They take phi (binary
+// model) from the buffer that the last step read: after a single step that is
+// phi of the state's own time, after a two-step launch the phi of the step
+// before (the one in between stays in LDS).  With two steps per launch the
+// binary model's last step is therefore a single step.
+lb_status run_steps(lb_ctx* c, long n, bool readable = true) {
     const int K = c->cfg.graph_steps;
     const int spl = steps_per_launch(c->cfg);
+    const bool tail = readable && spl == 2 && c->model == LB_BINARY && n > 0;
+    if (tail) --n;
     if (graphs_used(c, n)) {
         const int launches = K / spl;   // K is even
         while (n >= K) {
@@ -602,6 +611,11 @@ lb_status run_steps(lb_ctx* c, long n) {
         c->t += spl;
     }
     if (n > 0) {   // an odd step of a two-step schedule
+        enqueue_step(c, false, false);
+        c->cur ^= 1;
+        c->t += 1;
+    }
+    if (tail) {
         enqueue_step(c, false, false);
         c->cur ^= 1;
         c->t += 1;
@@ -1187,8 +1201,6 @@ lb_status lb_set_launch_config(lb_ctx* c, const lb_launch_config* cfg) {
     const int r = cfg->tile_rows;
     if (r != 1 && r != 2 && r != 4 && r != 8) return fail(LB_EINVAL, "tile_rows must be 1, 2, 4 or 8");
     if (cfg->schedule < 0 || cfg->schedule > 6) return fail(LB_EINVAL, "schedule must be 0, 1, 2, 3, 4, 5 or 6");
-    if (cfg->schedule == 5 && c->model != LB_VDW)
-        return fail(LB_EINVAL, "schedule 5 (two steps per sweep) is built for the van der Waals model only");
     if (cfg->schedule == 6 && c->model != LB_BINARY)
         return fail(LB_EINVAL, "schedule 6 (moment storage) is built for the binary model only");
     if (cfg->schedule == 2 && (cfg->persist_blocks_per_cu < 1 || cfg->persist_blocks_per_cu > 32))
@@ -1249,9 +1261,8 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     const int ar = orig.fp64_arith;   // the arithmetic is a choice of the caller, not tuned
     for (int ch : {6, 8, 12, 16, 32}) cand.push_back({orig.tile_rows, 3, 4, 0, ar, ch});
     for (int ch : {8, 12, 16, 32}) cand.push_back({orig.tile_rows, 4, 4, 0, ar, ch});
-    if (c->model == LB_VDW)
-        for (int ch : {8, 12, 16, 24, 32}) cand.push_back({orig.tile_rows, 5, 4, 0, ar, ch});
-    else
+    for (int ch : {8, 12, 16, 24, 32}) cand.push_back({orig.tile_rows, 5, 4, 0, ar, ch});
+    if (c->model == LB_BINARY)
         for (int ch : {16, 20, 24, 32}) cand.push_back({orig.tile_rows, 6, 4, 0, ar, ch});
     for (int r : {4, 8}) {
         cand.push_back({r, 1, 4, 0, ar, orig.chunk_rows});
@@ -1268,9 +1279,10 @@ lb_status lb_autotune(lb_ctx* c, int trial_steps, lb_launch_config* best, double
     for (const auto& cf0 : cand) {
         lb_launch_config cf = cf0;
         if ((st = lb_set_launch_config(c, &cf))) break;
-        if ((st = run_steps(c, 2))) break;  // warm-up
+        // (the state is restored afterwards: no read-out needs the last step single)
+        if ((st = run_steps(c, 2, false))) break;  // warm-up
         if (!hip_ok(hipEventRecord(c->ev0, c->stream), "hipEventRecord")) break;
-        if ((st = run_steps(c, trial_steps))) break;
+        if ((st = run_steps(c, trial_steps, false))) break;
         float ms = 0.f;
         if (!hip_ok(hipEventRecord(c->ev1, c->stream), "hipEventRecord") ||
             !hip_ok(hipEventSynchronize(c->ev1), "hipEventSynchronize") ||

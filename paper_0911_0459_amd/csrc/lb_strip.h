@@ -170,18 +170,24 @@ __device__ __forceinline__ void st(const Planes& q, float v, int voff, int soff)
                                           __builtin_amdgcn_readfirstlane(soff), 0);
 }
 
-// 1/x for a positive normal x in the collision's arithmetic type: in FP64 the
-// hardware FP32 reciprocal (relative error below 2^-22 after the rounding of x
-// to FP32) refined by one Newton step, which squares the relative error (below
-// 1e-13: far below the FP32 rounding of the stored state), with far fewer
-// instructions and registers than the correctly rounded division; in FP32 the
-// division itself.
+// 1/x for a positive normal x in the collision's arithmetic type: the
+// hardware FP32 reciprocal (1 ulp) refined by one Newton step, with far fewer
+// instructions and registers than the correctly rounded division.  In FP64 the
+// step squares the relative error of the FP32 estimate (below 2^-22 after the
+// rounding of x to FP32), leaving it below 1e-13, far below the FP32 rounding
+// of the stored state.  In FP32 the step's own FMA rounds the result to
+// within about half an ulp (the Newton step from either side lands below 1/x
+// by the square of the estimate's error, 1e-14 relative, so the rounding
+// carries no bias that a conserved quantity could accumulate).
 __device__ __forceinline__ double recip(double x) {
     const double r = (double)__builtin_amdgcn_rcpf((float)x);
     return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 }
 
-__device__ __forceinline__ float recip(float x) { return 1.f / x; }
+__device__ __forceinline__ float recip(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.f), r);
+}
 
 // Makes a uniform FP32 value opaque to loop-invariant code motion (an empty asm
 // statement that claims to modify it in its scalar register).  Material
@@ -320,7 +326,7 @@ __global__ void __launch_bounds__(SW) lb_strip_bin(StripArgs a) {
             const bool bnd = sm != 0u;
             m = moments_of(f, bnd);
             const float F = bnd ? 0.f : c.Fx;
-            const float inv_rho = 1.f / (c.rho_ref + m.drho);
+            const float inv_rho = recip(c.rho_ref + m.drho);
             ux = (m.jx + 0.5f * F) * inv_rho;
             uy = m.jy * inv_rho;
         } else {
@@ -520,9 +526,13 @@ __device__ __forceinline__ void vdw_node_collide(const CapDev& c, const Mom<floa
 // order parameter and the stencils of phi, the bulk pressure and interface
 // terms of X (Sec. 3.1), the phi-dependent relaxation rate of Eq. (nu) and the
 // MRT relaxation with the non-shear part in type CT, the shear part in ST.
+// uxf, uyf: the node's velocity as the sweep formed it from the same moments in
+// FP32 ((j + F/2) recip(rho)); the FP32 collision takes it as it is, the FP64
+// one forms its own.
 template <typename CT, typename ST, bool FORCE>
 __device__ __forceinline__ PostState<CT> bin_node_state(const CapDev& c, const Mom<float>& mom, unsigned sm,
-                                                        float phi, float dxf, float dyf, float lapf) {
+                                                        float phi, float dxf, float dyf, float lapf, float uxf,
+                                                        float uyf) {
     // constants of the FP64 part, converted where used (see uniform_opaque)
     CapDev cd = c;
     uniform_opaque(cd.kappa);
@@ -533,8 +543,15 @@ __device__ __forceinline__ PostState<CT> bin_node_state(const CapDev& c, const M
     const Mom<CT> mc{(CT)mom.drho, (CT)mom.jx, (CT)mom.jy, (CT)mom.pxx, (CT)mom.pxy};
     const CT F = (FORCE && !sm) ? (CT)cd.Fx : CT(0);
     const CT rho = (CT)cd.rho_ref + mc.drho;
-    const CT inv_rho = recip(rho);
-    const CT ux = (FORCE ? mc.jx + CT(0.5) * F : mc.jx) * inv_rho, uy = mc.jy * inv_rho;
+    CT ux, uy;
+    if constexpr (sizeof(CT) == 4) {
+        ux = uxf;
+        uy = uyf;
+    } else {
+        const CT inv_rho = recip(rho);
+        ux = (FORCE ? mc.jx + CT(0.5) * F : mc.jx) * inv_rho;
+        uy = mc.jy * inv_rho;
+    }
     const CT ph = (CT)phi, phib = (CT)cd.phib;
     const CT dX = mc.drho * (CT(1) / CT(3)) +
                   CT(0.25) * (CT)cd.B * ((ph - phib) * (ph + phib)) * (CT(3) * ph * ph + phib * phib) -

@@ -131,7 +131,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             const bool bnd = sm != 0u;
             m = moments_of(f, bnd);
             const float F = bnd ? 0.f : c.Fx;
-            const float inv_rho = 1.f / (c.rho_ref + m.drho);
+            const float inv_rho = recip(c.rho_ref + m.drho);
             ux = (m.jx + 0.5f * F) * inv_rho;
             uy = m.jy * inv_rho;
         } else {
@@ -225,11 +225,12 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
         lds_barrier();
         // (d) collision and phi update of row y (main lanes)
         if (out_col && fl_cur) {
-            // constants of the FP64 part, converted where used (see uniform_opaque)
             const int s0 = sl(0);
             const float phi = RG[s0][R_PH][pj];
+            const float uxf = RG[s0][R_UX][pj], uyf = RG[s0][R_UY][pj];
             CT o[9];
-            pops_of_state(bin_node_state<CT, ST, FORCE>(c, mom_cur, sm_cur, phi, dx_cur, dy_cur, lap_cur), o);
+            pops_of_state(bin_node_state<CT, ST, FORCE>(c, mom_cur, sm_cur, phi, dx_cur, dy_cur, lap_cur, uxf, uyf),
+                          o);
             const int srow = row_info(g, y).y0 * fd.rb;
 #pragma unroll
             for (int i = 0; i < 9; ++i) st(fd, (float)o[i], L.b0, i * fd.pb + srow);
@@ -237,7 +238,6 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wide_bin(StripArgs a) {
             // (its LDS reads would be hoisted into the collision's register peak)
             __builtin_amdgcn_sched_barrier(0);
             // phi(t+1) (phi_delta, as in lb_strip_bin)
-            const float uxf = RG[s0][R_UX][pj], uyf = RG[s0][R_UY][pj];
             const float dphi = phi_delta(sm_cur, phi, uxf, uyf, RG[s0][R_AM][pj],
                                          [&](int i, float& a, float& p, float& x, float& y) {
                                              const int sn = sl(-ey_(i)), kn = pj - ex_(i);

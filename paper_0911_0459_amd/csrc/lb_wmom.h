@@ -128,18 +128,26 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
         q.pm = ld(ps, L.b0, q.r.y0 * ps.rb);
     };
 
+    // what phase 2 leaves for the collision of its row in phase 3.  Two of them
+    // swap roles every row (the loop is unrolled by two); a lane that does not
+    // pull a row (a halo lane, a solid node) leaves the older contents, which
+    // no collision reads
+    struct Pulled {
+        Mom<float> mom;
+        float dx, dy, lap;   // stencils of phi
+    };
     Ahead A, B;
     request(s.ya - 2, A);
-    Mom<float> mom_cur{0.f, 0.f, 0.f, 0.f, 0.f};
+    Pulled PA{{0.f, 0.f, 0.f, 0.f, 0.f}, 0.f, 0.f, 0.f}, PB = PA;
     unsigned sm_cur = 0u;
     bool fl_cur = false;
-    float dx_cur = 0.f, dy_cur = 0.f, lap_cur = 0.f;
     float f0_cur = 0.f;   // f0 of row y+1 (this lane's column)
     // phi of this lane's column in fixed point, rows y+1 and y (the update adds to it)
     int q_next = 0, q_cur = 0;
 
-    // iteration y: n holds the requests for row y+2, p receives those for row y+3
-    auto iter = [&](int y, const Ahead& n, Ahead& p) {
+    // iteration y: n holds the requests for row y+2, p receives those for row y+3;
+    // cur holds row y's pulls, nxt receives row y+1's
+    auto iter = [&](int y, const Ahead& n, Ahead& p, const Pulled& cur, Pulled& nxt) {
         // ---- phase 1: requests for row y+3 (past the chunk's last rebuilt row,
         // yb+1, a repeat of it: cache hits, unused); row y+2 rebuilt, its phi
         request(y + 3 <= s.yb + 1 ? y + 3 : s.yb + 1, p);
@@ -163,11 +171,9 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
         }
         lds_barrier();
         // ---- phase 2: pulls, moments and u of row y+1; stencils and A of row y+1
-        Mom<float> mom_n{0.f, 0.f, 0.f, 0.f, 0.f};
         const RowInfo rn = row_info(g, y + 1);
         const unsigned sm_n = solid_bits(L, rn);
         const bool fl_n = !(L.t0 && rn.w0);
-        float dx_n = 0.f, dy_n = 0.f, lap_n = 0.f;
         if (y >= s.ya - 2 && W.um) {
             float ux = 0.f, uy = 0.f, am = 0.f;
             if (fl_n) {
@@ -206,14 +212,14 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
                     f[i] = *(bb ? own(opp_(i)) : src(i));
                 }
                 const bool bnd = sm_n != 0u;
-                mom_n = moments_of(f, bnd);
+                nxt.mom = moments_of(f, bnd);
                 const float F = bnd ? 0.f : c.Fx;
-                const float inv_rho = 1.f / (c.rho_ref + mom_n.drho);
-                ux = (mom_n.jx + 0.5f * F) * inv_rho;
-                uy = mom_n.jy * inv_rho;
-                stencil3(PH[m6(0)], PH[m6(1)], PH[m6(2)], qj, sm_n, G2, dx_n, dy_n, lap_n);
+                const float inv_rho = recip(c.rho_ref + nxt.mom.drho);
+                ux = (nxt.mom.jx + 0.5f * F) * inv_rho;
+                uy = nxt.mom.jy * inv_rho;
+                stencil3(PH[m6(0)], PH[m6(1)], PH[m6(2)], qj, sm_n, G2, nxt.dx, nxt.dy, nxt.lap);
                 const float ph = PH[m6(1)][qj];
-                const float gmu = Gam * (mu_bulk(c, ph) - kap * lap_n);
+                const float gmu = Gam * (mu_bulk(c, ph) - kap * nxt.lap);
                 am = gmu - 0.5f * ph * (ux * ux + uy * uy);
             }
             const int u1 = m3(1);
@@ -225,7 +231,10 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
         // ---- phase 3: collision and phi update of row y (main lanes)
         if (y >= s.ya && out_col && fl_cur) {
             const float phi = PH[m6(0)][pj];
-            const PostState<CT> st8 = bin_node_state<CT, ST, FORCE>(c, mom_cur, sm_cur, phi, dx_cur, dy_cur, lap_cur);
+            const int u0 = m3(0);
+            const float uxf = UA[u0][0][pj], uyf = UA[u0][1][pj];
+            const PostState<CT> st8 =
+                bin_node_state<CT, ST, FORCE>(c, cur.mom, sm_cur, phi, cur.dx, cur.dy, cur.lap, uxf, uyf);
             const int srow = row_info(g, y).y0 * md.rb;
             st(md, (float)st8.drho, L.b0, 0 * md.pb + srow);
             st(md, (float)third(st8.jx), L.b0, 1 * md.pb + srow);
@@ -237,8 +246,7 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
             // the phi update below is not to be interleaved with the collision
             // (its LDS reads would be hoisted into the collision's register peak)
             __builtin_amdgcn_sched_barrier(0);
-            const int u0 = m3(0);
-            const float dphi = phi_delta(sm_cur, phi, UA[u0][0][pj], UA[u0][1][pj], UA[u0][2][pj],
+            const float dphi = phi_delta(sm_cur, phi, uxf, uyf, UA[u0][2][pj],
                                          [&](int i, float& am, float& pp, float& x, float& yy) {
                                              const int un = m3(-ey_(i)), kn = pj - ex_(i);
                                              am = UA[un][2][kn];
@@ -249,21 +257,17 @@ __global__ void __launch_bounds__(WIDE_THREADS, 6) lb_wmom_bin(StripArgs a) {
             st(pd, phi_bits(q_cur + fixed_of_phi(dphi)), L.b0, srow);
         }
         // ---- rotate the row state
-        mom_cur = mom_n;
         sm_cur = sm_n;
         fl_cur = fl_n;
-        dx_cur = dx_n;
-        dy_cur = dy_n;
-        lap_cur = lap_n;
         f0_cur = f0_next;
         q_cur = q_next;
         q_next = q_new;
         t6 = t6 == 5 ? 0 : t6 + 1;
     };
     for (int y = s.ya - 4; y < s.yb; y += 2) {
-        iter(y, A, B);
+        iter(y, A, B, PA, PB);
         if (y + 1 >= s.yb) break;
-        iter(y + 1, B, A);
+        iter(y + 1, B, A, PB, PA);
     }
 }
 

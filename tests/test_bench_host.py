@@ -71,7 +71,9 @@ def test_algorithmic_and_stored_bytes():
     binary moment storage (schedule 6) itself moves 64 B."""
     import bench
     assert bench.BYTES_PER_LUP == {"vdw": 72, "binary": 80}
-    assert bench.stored_bytes_per_lup("vdw", 5) == 72
+    assert bench.stored_bytes_per_lup("vdw", 5) == 36
+    assert bench.stored_bytes_per_lup("binary", 5) == 40
+    assert bench.stored_bytes_per_lup("vdw", 4) == 72
     assert bench.stored_bytes_per_lup("binary", 4) == 80
     assert bench.stored_bytes_per_lup("binary", 6) == 64
 

@@ -69,7 +69,8 @@ def test_binary_capillary_1e4_steps(L):
     """Binary capillary (ratio 10, 60 degrees) on a 256x64 lattice."""
     w = small_binary()
     orc, lo = run_oracle(w, 10_000, sample_every=500)
-    for cfg in (dict(schedule=4, chunk_rows=8), None):   # population storage; the default, moment storage
+    # population storage; two steps per sweep; the default, moment storage
+    for cfg in (dict(schedule=4, chunk_rows=8), dict(schedule=5, chunk_rows=16), None):
         gpu, lg = gpu_run(L, w, 10_000, sample_every=500, cfg=cfg)
         drho, dphi, du = field_errors(w, gpu, orc)
         print(f"binary 1e4 {cfg}: max rel drho {drho:.3e}, max dphi {dphi:.3e}, du {du:.3e}, "
@@ -87,7 +88,8 @@ def test_binary_capillary_1024x128_1e4_steps(L):
     print(f"binary 1024x128 1e4: oracle run", flush=True)
     orc, lo = run_oracle(w, 10_000, sample_every=500)
     assert lo[-1] > lo[0] + 5.0          # the liquid is filling the tube
-    for cfg in (dict(schedule=4, chunk_rows=8), None):   # population storage; the default, moment storage
+    # population storage; two steps per sweep; the default, moment storage
+    for cfg in (dict(schedule=4, chunk_rows=8), dict(schedule=5, chunk_rows=16), None):
         print(f"binary 1024x128 1e4: GPU run {cfg}", flush=True)
         gpu, lg = gpu_run(L, w, 10_000, sample_every=500, cfg=cfg)
         drho, dphi, du = field_errors(w, gpu, orc)
@@ -576,7 +578,7 @@ def test_graph_replays_equal_direct_launches(L):
         rep.close()
 
 
-# ---- two time steps per sweep (schedule 5, van der Waals) ----------------------
+# ---- two time steps per sweep (schedule 5), van der Waals model -----------------
 FUSED_GEOMS = {
     "ragged150x37": I.Geometry(nx=150, ny=37, x_in=53, tube_len=97, tube_h=13, y0=11),
     "wide700x45": I.Geometry(nx=700, ny=45, x_in=250, tube_len=450, tube_h=17, y0=14),
@@ -662,10 +664,139 @@ def test_vdw_capillary_256x64_1e4_steps_fused(L):
     assert np.abs(lg - lo).max() <= 0.5
 
 
-def test_fused_schedule_is_refused_for_the_binary_model(L):
-    w = small_binary(nx=130, ny=40, H=12)
-    lat = L.Lattice(L.params_from_workload(w), L.geometry_from_workload(w), w.initial_field())
-    with pytest.raises(L.LbError) as e:
-        lat.set_launch_config(schedule=5, chunk_rows=8)
-    assert e.value.code == L.LB_EINVAL
+# ---- two time steps per sweep, binary model ----------------------------------
+@pytest.mark.parametrize("name", list(FUSED_GEOMS))
+def test_fused_binary_equals_single_steps_and_oracle(L, name):
+    """Schedule 5 for the binary model (two steps per sweep; f*(t) and
+    phi(t+1) in LDS, with a halo of four nodes): bitwise the same whatever the
+    chunking (0, 5, 12, 24 rows), with graphs or direct launches, in either
+    arithmetic; against single-step wide strips to rounding (the same
+    arithmetic per step, compiled apart: single nodes differ in the last bit
+    after a few steps); against the oracle at the short-run tolerances."""
+    g = FUSED_GEOMS[name]
+    nl, ng = I.viscosity_pair(30.0)
+    wet = dict(theta_deg=45.0) if g.tube_h else dict(wall_grad=0.0)
+    w = I.Workload(f"bin_fused_{name}", "binary", g, 0, 0, seed=73, nu_l=nl, nu_g=ng, liquid=1.0, gas=-1.0,
+                   **wet, **I.BIN_CONSTS)
+    init = None
+    if name == "periodic5x3":
+        init = np.array([[1.0, 0.8, -0.2, -1.0, -0.9], [0.9, 0.7, 0.1, -0.8, -1.0], [1.0, 0.6, -0.3, -0.9, -0.7]])
+    steps = 201
+    for arith in (1, 0):
+        print(f"fused binary {name}: single-step reference, fp64_arith {arith}", flush=True)
+        ref, _ = gpu_run(L, w, steps, cfg=dict(schedule=4, chunk_rows=8, graph_steps=0, fp64_arith=arith), init=init)
+        first = None
+        for cfg in (dict(schedule=5, chunk_rows=0, graph_steps=64), dict(schedule=5, chunk_rows=5, graph_steps=0),
+                    dict(schedule=5, chunk_rows=12, graph_steps=2), dict(schedule=5, chunk_rows=24, graph_steps=64)):
+            got, _ = gpu_run(L, w, steps, cfg=dict(cfg, fp64_arith=arith), init=init)
+            if first is None:
+                first = got
+                gap = max(float(np.abs(x - y).max()) for x, y in zip(ref, got))
+                print(f"fused binary {name}: fp64_arith {arith}: max |difference| to single steps {gap:.3e}",
+                      flush=True)
+                assert gap <= 2e-6, (arith, gap)
+            else:
+                for x, y in zip(first, got):
+                    assert np.array_equal(x, y), (cfg, arith)
+        orc, _ = run_oracle(w, steps, init=init)
+        drho, dphi, du = field_errors(w, first, orc)
+        assert drho < 2e-5 and dphi < 2e-5 and du < 1e-6, (arith, drho, dphi, du)
+
+
+def test_fused_binary_graph_replays_batch_and_sampling(L):
+    """Binary schedule 5 run from graphs interleaved with direct launches, odd
+    step counts and host reads: bitwise the same calls made with direct
+    launches (every call ends with a single step, so that the read-outs see phi
+    of the state's time), and the single-step run to rounding.  A batch of two
+    capillaries with one retired for a while: each equals its single run
+    bitwise, and the filled lengths sampled every 25 steps agree with those of
+    the single-step strips."""
+    w = small_binary(nx=200, ny=48, H=16, seed=87)
+    p = L.params_from_workload(w)
+    g = L.geometry_from_workload(w)
+    calls = (64, 70, 64, 1, 101)
+    direct = L.Lattice(p, g, w.initial_field())
+    direct.set_launch_config(schedule=5, chunk_rows=12, graph_steps=0)
+    for n in calls:
+        direct.step(n)
+    ref = direct.moments()
+    direct.close()
+    single = L.Lattice(p, g, w.initial_field())
+    single.set_launch_config(schedule=4, chunk_rows=8, graph_steps=0)
+    single.step(300)
+    gap = max(float(np.abs(x - y).max()) for x, y in zip(single.moments(), ref))
+    single.close()
+    print(f"fused binary 300 steps: max |difference| to single steps {gap:.3e}")
+    assert gap <= 2e-6
+    rep = L.Lattice(p, g, w.initial_field())
+    rep.set_launch_config(schedule=5, chunk_rows=12, graph_steps=64)
+    for n in calls:
+        rep.step(n)
+        rep.interface_length()
+        rep.moments()
+    assert rep.t == 300
+    rep.check()
+    for x, y in zip(rep.moments(), ref):
+        assert np.array_equal(x, y)
+    rep.close()
+
+    ws = [small_binary(nx=160, ny=40, H=12, seed=s) for s in (88, 89)]
+    P = [L.params_from_workload(v) for v in ws]
+    G = [L.geometry_from_workload(v) for v in ws]
+    Q = [v.initial_field() for v in ws]
+    F5 = dict(schedule=5, chunk_rows=16, graph_steps=64)
+    b = L.Lattice(P, G, Q)
+    b.set_launch_config(**F5)
+    b.step(101)
+    frozen = b.moments(1)
+    b.retire(1)
+    b.step(51)
+    for x, y in zip(frozen, b.moments(1)):
+        assert np.array_equal(x, y)
+    b.revive(1)
+    b.step(99)
+    for k, ns in ((0, (101, 51, 99)), (1, (101, 99))):   # the same calls (capillary 1 retired for one)
+        single = L.Lattice(P[k], G[k], Q[k])
+        single.set_launch_config(**F5)
+        for n in ns:
+            single.step(n)
+        for x, y in zip(single.moments(), b.moments(k)):
+            assert np.array_equal(x, y), k
+        single.close()
+    b.close()
+    hists = []
+    for shape in (dict(schedule=4, chunk_rows=8), dict(schedule=5, chunk_rows=16)):
+        bb = L.Lattice(P, G, Q)
+        bb.set_launch_config(**shape, graph_steps=64)
+        bb.step(275, sample_every=25)
+        hists.append([bb.l_history(k) for k in range(2)])
+        bb.close()
+    for (t0, h0), (t1, h1) in zip(*hists):
+        assert list(t0) == list(t1) == list(range(25, 276, 25))
+        assert np.abs(h0 - h1).max() <= 1e-4
+
+
+def test_fused_binary_storage_switches(L):
+    """Switching between the two-step sweep (population storage) and the
+    moment storage mid-run converts the state; the result agrees with the
+    single-step population storage to rounding."""
+    w = small_binary(nx=200, ny=48, H=16, seed=91)
+    p = L.params_from_workload(w)
+    g = L.geometry_from_workload(w)
+    ref = L.Lattice(p, g, w.initial_field())
+    ref.set_launch_config(schedule=4, chunk_rows=8, graph_steps=64)
+    ref.step(181)
+    want = ref.moments()
+    ref.close()
+    lat = L.Lattice(p, g, w.initial_field())
+    for cfg, n in ((dict(schedule=5, chunk_rows=16), 60), (dict(schedule=6, chunk_rows=20), 61),
+                   (dict(schedule=5, chunk_rows=12), 60)):
+        lat.set_launch_config(**cfg, graph_steps=64)
+        lat.step(n)
+    assert lat.t == 181
+    got = lat.moments()
+    lat.check()
     lat.close()
+    gap = max(float(np.abs(x - y).max()) for x, y in zip(want, got))
+    print(f"fused/moment storage switches: max |difference| {gap:.3e}")
+    assert gap <= 2e-6
