@@ -296,9 +296,13 @@ long long lb_fluid_nodes(const lb_ctx* c);
  *    reads the populations (and phi) once with a halo of three nodes (binary
  *    model: four), keeps the intermediate step in LDS and writes the second
  *    step, so that the populations cross HBM once per two steps; an odd step
- *    count ends with one launch of schedule 4.  The same arithmetic per step
- *    as schedule 4 (the intermediate step rounded to FP32, phi to its fixed
- *    point, as a single step stores them).
+ *    count ends with one launch of schedule 4, and with the binary model every
+ *    stepping call does (the read-outs take phi of the step the last launch
+ *    read, which a two-step launch leaves one step behind).  The same
+ *    arithmetic per step as schedule 4 (the intermediate step rounded to
+ *    FP32, phi to its fixed point, as a single step stores them): van der
+ *    Waals results are bitwise those of schedule 4, binary ones agree to
+ *    rounding.
  *    6 (binary model only; its default) the strips of 4 over a stored state of seven FP32
  *    planes instead of nine populations: with the rates of Appendix A the
  *    post-collision populations of a node follow from rho - rho_ref, j* / 3, the
