@@ -319,14 +319,23 @@ def test_row_sweeps_do_not_depend_on_the_chunking(L, model, schedule):
             assert np.array_equal(x, y), (model, schedule, ch)
 
 
-def test_checkpoint_resume_is_bitwise(L):
+@pytest.mark.parametrize("cfg", [None, dict(schedule=5, chunk_rows=16)], ids=["default", "two_steps_per_sweep"])
+def test_checkpoint_resume_is_bitwise(L, cfg):
+    """A checkpoint taken after 120 steps, resumed elsewhere, ends bitwise
+    where the run without it ends (the same stepping calls: with two steps per
+    sweep each call of the binary model ends with a single step)."""
     w = small_binary(nx=200, ny=48, H=16)
     p = L.params_from_workload(w, wall_grad=oracle_wall_grad(w))
     g = L.geometry_from_workload(w)
     ref = L.Lattice(p, g, w.initial_field())
-    ref.step(300)
+    if cfg:
+        ref.set_launch_config(**cfg)
+    ref.step(120)
+    ref.step(180)
     full = ref.moments()
     lat = L.Lattice(p, g, w.initial_field())
+    if cfg:
+        lat.set_launch_config(**cfg)
     lat.step(120)
     blob = lat.save()
     lat.step(77)                     # wander off, then come back
