@@ -305,6 +305,33 @@ def test_init_is_equilibrium_and_rest_stops_boundary_nodes():
     assert np.abs(ux[~bnd & ~s]).max() > 1e-6
 
 
+@pytest.mark.parametrize("wall_grad", [0.0, -0.2])
+def test_binary_step_conserves_mass_and_order_parameter(wall_grad):
+    """With the g populations eliminated (Appendix A: every g rate is 1), phi
+    at a node is the sum of the g^eq_i streamed in from its fluid neighbours
+    plus the bounce-back g^eq_opp of its own for solid ones (Eq. latbolt, the
+    bounce-back of Sec. 2.2).  Every g^eq_i(r) then arrives at exactly one
+    node, so the total of phi over the fluid nodes is that of the step
+    before, for any wall gradient; the f populations keep the total mass the
+    same way (the rest condition leaves rho).  A lost or duplicated
+    population (a dropped bounce-back term, or one streamed twice) breaks the
+    first; which of g^eq_i and g^eq_opp(i) bounces back is not seen here, since
+    the rest condition makes them equal at boundary nodes."""
+    g = OracleGeom(nx=48, ny=20, x_in=16, tube_len=24, tube_h=8, y0=6)
+    x = np.arange(48)
+    rng = np.random.default_rng(7)
+    q0 = np.where(x[None, :] < 26, 1.0, -1.0) * np.ones((20, 48)) + rng.uniform(-0.05, 0.05, (20, 48))
+    o = Oracle(OracleParams(**{**BIN.__dict__, "wall_grad": wall_grad}), g, q0)
+    s = solid_mask(g)
+    rho, _, _, phi = o.moments()
+    m0, p0 = rho[~s].sum(), phi[~s].sum()
+    o.step(300)
+    rho, ux, uy, phi = o.moments()
+    assert np.hypot(ux, uy).max() > 1e-5            # the fluid moves
+    assert abs(rho[~s].sum() - m0) / m0 < 1e-12
+    assert abs(phi[~s].sum() - p0) < 1e-10 * np.abs(phi[~s]).sum()
+
+
 def test_interface_length_definition():
     """Filled length: linear interpolation of the first centreline crossing."""
     g = OracleGeom(nx=30, ny=12, x_in=10, tube_len=20, tube_h=4, y0=4)
