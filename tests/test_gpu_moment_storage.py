@@ -191,17 +191,20 @@ def test_moment_storage_is_refused_for_the_vdw_model(L):
     lat.close()
 
 
-def test_full_sweep_in_the_bench_shape_matches_oracle_on_sampled_capillaries(L):
+@pytest.mark.parametrize("shape", [dict(schedule=6, chunk_rows=20), dict(schedule=5, chunk_rows=48)],
+                         ids=["moment_storage", "two_steps_per_sweep"])
+def test_full_sweep_in_the_bench_shape_matches_oracle_on_sampled_capillaries(L, shape):
     """The benchmark's workload at its full size (the 256 uneven capillaries of
     the sweep, 32.95 M fluid nodes) in the launch shape the bench times
-    (moment storage, chunks of 20 rows, 64-step graphs), sampled: after 400
-    steps the two smallest capillaries, a middle one and the largest agree
-    with the oracle run on each alone, at the short-run tolerances, and their
-    filled lengths, sampled every 100 steps, within 0.05."""
+    (moment storage, chunks of 20 rows, 64-step graphs) and in the two-step
+    sweep the autotuner also tries there, sampled: after 400 steps the two
+    smallest capillaries, a middle one and the largest agree with the oracle
+    run on each alone, at the short-run tolerances, and their filled lengths,
+    sampled every 100 steps, within 0.05."""
     ws = I.sweep_batch(4, 256)
     lat = L.Lattice([L.params_from_workload(w) for w in ws], [L.geometry_from_workload(w) for w in ws],
                     [w.initial_field() for w in ws])
-    lat.set_launch_config(schedule=6, chunk_rows=20, graph_steps=64)
+    lat.set_launch_config(**shape, graph_steps=64)
     lat.step(400, sample_every=100)
     lat.check()
     fluid = [int((~w.geom.solid()).sum()) for w in ws]
