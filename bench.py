@@ -326,7 +326,7 @@ def main():
     lat = L.Lattice(params[0], geoms[0], fields[0]) if len(works) == 1 else L.Lattice(params, geoms, fields)
     del fields
     if not args.no_autotune:
-        cfg, _ = lat.autotune(trial_steps=32)   # longer trials: chunkings 1 % apart are told apart
+        cfg, _ = lat.autotune(trial_steps=128)   # long trials: chunkings 1 % apart are told apart
     cfg = lat.launch_config()
     if args.tile_rows or args.schedule >= 0 or args.fp64_arith >= 0 or args.chunk_rows >= 0 or args.graph_steps >= 0:
         lat.set_launch_config(args.tile_rows or cfg.tile_rows, cfg.schedule if args.schedule < 0 else args.schedule,
