@@ -226,14 +226,17 @@ def test_lambda_off_and_full_periodic_box(L):
         assert drho < 2e-5 and du < 1e-6
 
 
-def test_poiseuille_body_force_narrow_lattice(L):
-    """nx = 3 (narrower than one tile) with the Guo body force."""
+@pytest.mark.parametrize("cfg", [None, dict(schedule=4, chunk_rows=8), dict(schedule=5, chunk_rows=8)],
+                         ids=["default", "populations", "two_steps_per_sweep"])
+def test_poiseuille_body_force_narrow_lattice(L, cfg):
+    """nx = 3 (narrower than one tile, and than the halo of the two-step sweep)
+    with the Guo body force, in each binary row sweep."""
     H = 20
     g = I.Geometry(nx=3, ny=H + 2, x_in=0, tube_len=3, tube_h=H, y0=1)
     w = I.Workload("pois", "binary", g, 0, 0, seed=24, nu_l=1 / 6, nu_g=1 / 6, wall_grad=0.0, liquid=1.0,
                    gas=1.0, noise=0.0, **I.BIN_CONSTS)
     init = np.ones((H + 2, 3))
-    gpu, _ = gpu_run(L, w, 3000, init=init, force_x=1e-5)
+    gpu, _ = gpu_run(L, w, 3000, cfg=cfg, init=init, force_x=1e-5)
     orc, _ = run_oracle(w, 3000, init=init, force_x=1e-5)
     rho, ux, _, _ = gpu
     assert np.abs(ux - orc[1]).max() / np.abs(orc[1]).max() < 1e-4
